@@ -1,0 +1,165 @@
+"""Benchmark of the M-rPIE hot path on one MI355X.
+
+Workload (default): the mixed-state Fermat-spiral scan — 1024^2 complex64
+object, 256^2 probe with 3 modes, 1600 positions (~70 % overlap), float32
+Poisson intensities at 1e7 photons per pattern, synthetic and seeded.
+A step is one full rPIE iteration over all 1600 positions (gather, exit
+waves, forward FFT, modulus replacement, inverse FFT, probe and object
+updates) with every input resident in HBM.  The metric is positions x
+iterations per second.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--positions", type=int, default=1600, help="scan length (default: the full 1600)")
+    ap.add_argument("--timing-stride", type=int, default=16,
+                    help="sample every n-th launch of each kernel with HIP events")
+    ap.add_argument("--cpu-positions", type=int, default=400,
+                    help="positions in the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(N, M):
+    """Bytes one position must move: read o_j, P, I_j; write o_j, P."""
+    rows = 16 * N * N * (M + 1)      # k_rows: o and P read + written
+    cols = 4 * N * N                 # k_cols: I_j read
+    return rows, cols
+
+
+def cpu_baseline(w, npos):
+    """The FP64 oracle timed on this host on the first `npos` positions of
+    one iteration (single-threaded numpy FFT)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    prm = oracle.Params(**dict(w.params, iterations=1))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.rpie64(w.O0, w.P0, w.pos0[:npos], w.I[:npos], prm)
+        dt = time.perf_counter() - t0
+    return dict(value=npos / dt, unit="positions*iter/s", cores=1, kind="oracle",
+                sample=f"first {npos} of 1600 positions, 1 iteration, FP64 numpy, 1 thread",
+                seconds=round(dt, 3))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2205_04295_amd import api
+    from synth import workloads as wl
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = wl.spiral_case(seed=1, J=args.positions)
+    gen_s = time.time() - t0
+    M, N, _ = w.P0.shape
+    J = w.pos0.shape[0]
+    obj = torch.from_numpy(w.O0).to(dev)
+    probe = torch.from_numpy(w.P0).to(dev)
+    pos = torch.from_numpy(w.pos0).to(dev)
+    I = torch.from_numpy(w.I).to(dev)
+    err = torch.zeros(1, dtype=torch.float32, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    prm = dict(w.params)
+    prm.pop("iterations", None)
+
+    ws = None
+    for it in range(args.warmup):
+        ws = api.rpie(obj, probe, pos, I, err=err, status=status, workspace=ws, iterations=1,
+                      iter_offset=it, **prm)
+    torch.cuda.synchronize()
+
+    api.timing_enable(args.timing_stride)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ws = api.rpie(obj, probe, pos, I, err=err, status=status, workspace=ws, iterations=1,
+                      iter_offset=args.warmup + k, **prm)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kt = api.timing_read()
+    api.timing_enable(0)
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = J * args.steps / elapsed
+    rows_b, cols_b = algorithmic_bytes(N, M)
+    per_launch = {"k_rows": rows_b, "k_cols": cols_b}
+    # dominant kernel: largest total time per step (one launch of each per position)
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms = kt[dom][0]
+    achieved = per_launch[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    # whole-path algorithmic bandwidth (all kernels of a step)
+    path_gbs = (rows_b + cols_b) * J / (ms_per_step * 1e-3) / 1e9
+
+    if args.calib:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if args.cpu_positions > 0:
+        cpu = cpu_baseline(w, min(args.cpu_positions, J))
+        cpu["cores"] = 1
+        cpu["host_cpus"] = os.cpu_count()
+
+    line = {
+        "metric": "rPIE positions*iter/s (256^2 probe, 3 modes, 1600-point spiral, plain sweep)",
+        "value": round(value, 1),
+        "unit": "positions*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded virtual experiment, Poisson 1e7 photons/pattern)",
+        "config": {"workload": "spiral256x3: object 1024^2, probe 256^2 x 3 modes, 1600 positions, "
+                               "1 iteration per step, plain sequential sweep",
+                   "positions": J, "N": N, "M": M, "object": list(w.O0.shape),
+                   "params": {k: v for k, v in w.params.items()}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": dom, "kernel_avg_us": round(dom_ms * 1e3, 3),
+                     "algorithmic_bytes_per_launch": per_launch[dom],
+                     "launches_timed": int(kt[dom][1])},
+        "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
+        "path_algorithmic_GBs": round(path_gbs, 1),
+        "cpu_baseline": cpu,
+        "status": int(status.item()),
+        "final_error": float(err.item()),
+        "datagen_s": round(gen_s, 1),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/* mrpie.h — C ABI of the MI355X (gfx950) multi-mode rPIE hot path.
+ *
+ * Method: Guzzi et al., "A modular software framework for the design and
+ * implementation of ptychography algorithms" (SciComPty), arXiv 2205.04295,
+ * Methods section: the mixed-state forward model (Eq. 1-4), the M-rPIE
+ * object/probe updates (Eq. 5-6) with the modulus-corrected wave (Eq. 7),
+ * and the Adam-driven cross-correlation position refinement (Eq. 8-9,
+ * Alg. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex arrays are complex64: interleaved (re, im) float pairs,
+ *    C-contiguous (last index fastest).  Real arrays are float32.
+ *  - Every array argument is DEVICE memory owned by the caller; the library
+ *    never allocates, frees or keeps a pointer after the call returns.
+ *    Scratch comes from a caller-provided device workspace whose size the
+ *    matching *_workspace_size function returns (0 when none is needed).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
+ *    default stream) and performs no host<->device synchronisation and no
+ *    allocation, so it may be recorded into a HIP graph.
+ *  - The object O is [H][W]; probe modes P are [M][N][N]; positions are
+ *    [J][2] floats (y, x): the top-left corner of the N x N box in object
+ *    pixels; diffraction intensities are [J][N][N] in FFT order (zero
+ *    frequency at [0][0], no fftshift).
+ *  - The far-field propagator D_z (Eq. 2) is the unitary 2-D DFT.
+ *  - Return codes: MRPIE_OK, or a negative MRPIE_E* code for errors found
+ *    on the host before anything is launched (then nothing is launched and
+ *    mrpie_last_error() gives a message, per calling thread).  Numerical
+ *    trouble found on the device while running sets bits in the
+ *    caller-provided int32 `status` word (never cleared by the library).
+ *  - Calls on distinct workspaces are reentrant.  Calls sharing one
+ *    workspace must be ordered on one stream.
+ */
+#ifndef MRPIE_H
+#define MRPIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MRPIE_OK 0
+#define MRPIE_EINVAL (-1)       /* bad shape, parameter or null pointer */
+#define MRPIE_EUNSUPPORTED (-2) /* N not in {64,128,192,256} or M > 8 */
+#define MRPIE_EDEVICE (-3)      /* HIP runtime error (message in mrpie_last_error) */
+#define MRPIE_EWORKSPACE (-4)   /* workspace missing or too small */
+
+/* device status bits (OR-ed into *status) */
+#define MRPIE_STATUS_NONFINITE 1   /* a NaN/Inf reached the object, probe or error */
+#define MRPIE_STATUS_POS_CLAMPED 2 /* a box corner was outside [0,H-N]x[0,W-N]
+                                      (or not finite) and was clamped */
+
+#define MRPIE_MAX_MODES 8
+
+/* Problem shape.  H, W: object rows / columns; N: probe side (64, 128, 192
+ * or 256); M: number of mutually incoherent probe modes (1..8, Eq. 4);
+ * J: number of scan positions. */
+typedef struct {
+  int32_t H, W, N, M, J;
+} mrpie_problem;
+
+/* Reconstruction parameters.
+ *  alpha_obj, alpha_probe : step sizes alpha_O, alpha_P (Eq. 6, Eq. 5)
+ *  beta  : probe-denominator weight, beta |o_j|^2_max + (1-beta)|o_j|^2
+ *          (Eq. 5), in [0, 1]
+ *  gamma : object-denominator weight, gamma (sum_p|P_p|^2)_max +
+ *          (1-gamma) sum_p|P_p|^2 (Eq. 6), in [0, 1].
+ *          beta = gamma = 1 is M-ePIE.
+ *  iterations : number of sweeps over all positions, in scan order
+ *  iter_offset: absolute index of the first iteration (resume); it drives
+ *          probe_update_start, refine_start and Adam's step counter
+ *  probe_update_start: the probe is updated only in iterations >= this
+ *  subpixel : 0 = crop at the nearest integer corner floor(pos + 0.5);
+ *          1 = also move the crop by the fractional part with a Fourier
+ *          phase ramp and move the object update back by the same amount
+ *  refine : 1 = XCORR_A position refinement (register o_j against the
+ *          updated o'_j, Adam step per position, Eq. 8-9 and Alg. 1) in
+ *          iterations >= refine_start
+ *  upsample : registration upsampling factor (window ceil(1.5 up) samples)
+ *  xcorr_norm: 0 = plain cross-power spectrum, 1 = phase-normalised
+ *  adam_lr, adam_b1, adam_b2, adam_eps : Adam hyper-parameters          */
+typedef struct {
+  float alpha_obj, alpha_probe, beta, gamma;
+  int32_t iterations, iter_offset, probe_update_start;
+  int32_t subpixel;
+  int32_t refine, refine_start, upsample, xcorr_norm;
+  float adam_lr, adam_b1, adam_b2, adam_eps;
+} mrpie_params;
+
+/* Library version string (static storage). */
+const char* mrpie_version(void);
+
+/* Message for the last error returned on the calling thread ("" if none). */
+const char* mrpie_last_error(void);
+
+/* Host-only check of a problem and parameter set (no GPU needed).
+ * Returns MRPIE_OK, MRPIE_EINVAL or MRPIE_EUNSUPPORTED. */
+int mrpie_validate(const mrpie_problem* pb, const mrpie_params* pr);
+
+/* Bytes of device workspace mrpie_rpie needs for (pb, pr); host-only. */
+int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t* bytes);
+
+/* The sequential M-rPIE sweep (Methods, "M-rPIE algorithm"; Eq. 4-7, with
+ * Eq. 8-9 / Alg. 1 when pr->refine = 1).
+ *
+ * For it in [0, iterations) and j in [0, J) in order: gather o_j from obj at
+ * pos[j]; form psi_p = P_p o_j for every mode; Psi_p = D_z psi_p; replace
+ * the mode-summed modulus by sqrt(intens[j]) (zero where the model is 0;
+ * intensities are clamped at 0); psi'_p = D_{-z} Psi'_p; update the probe
+ * (Eq. 5) and the object box (Eq. 6) simultaneously from the pre-update
+ * o_j and P_p.
+ *
+ *  obj    [H][W]    complex64, in/out
+ *  probe  [M][N][N] complex64, in/out
+ *  pos    [J][2]    float32, in (in/out when refine = 1)
+ *  adam   [J][4]    float32 (m_y, m_x, v_y, v_x), in/out when refine = 1,
+ *                   may be NULL otherwise
+ *  intens [J][N][N] float32, in
+ *  err_out[iterations] float32, out: sum_j sum (|Psi| - sqrt(I))^2 /
+ *                   sum_j sum I for each iteration (may be NULL)
+ *  status int32, OR-ed with MRPIE_STATUS_* bits (may be NULL)
+ *  ws, ws_bytes     workspace of at least mrpie_workspace_size bytes
+ * The result is deterministic: the same inputs give bitwise equal outputs. */
+int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void* probe,
+               float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Test hook: in-place unitary 2-D DFT (D_z, Eq. 2; inverse = 1 gives
+ * D_{-z}) of B contiguous N x N complex64 arrays.  N in {64,128,192,256}. */
+int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream);
+
+/* Test hook: in-place modulus replacement of Eq. 7 on M detector-plane
+ * modes Psi [M][N][N] (unitary scale) with intensity I [N][N]:
+ * Psi_p <- sqrt(max(I,0)) / sqrt(sum_n |Psi_n|^2) * Psi_p, 0 where the sum
+ * is 0. */
+int mrpie_modulus(int32_t N, int32_t M, void* psi, const float* intens, void* stream);
+
+/* Diagnostic kernel timing (not for use under graph capture).
+ * mrpie_timing_enable(stride): from now on, every stride-th launch of each
+ * timed kernel class is bracketed by a HIP event pair on the stream it is
+ * launched on (stride = 0 switches timing off).  Classes: 0 = sweep row
+ * pass (k_rows), 1 = sweep column pass (k_cols).
+ * mrpie_timing_read(avg_ms[nkinds], count[nkinds], nkinds): waits for the
+ * recorded events, returns the mean duration and number of timed launches
+ * per class, and clears the record.  Host-side state, one per process. */
+int mrpie_timing_enable(int32_t stride);
+int mrpie_timing_read(double* avg_ms, int64_t* count, int32_t nkinds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRPIE_H */

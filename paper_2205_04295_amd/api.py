@@ -1,0 +1,113 @@
+"""Thin torch-facing wrappers over the libmrpie C ABI.
+
+torch provides device memory and the current stream; every computation runs
+in the HIP library.  Functions take CUDA (HIP) tensors and pass their data
+pointers; they raise if the library is missing or a tensor is not on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _abi
+from ._abi import Problem, check, make_params
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, name):
+    return C.c_void_p(None) if t is None else _dev(t, dtype, name)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def problem_of(obj, probe, pos):
+    M, N, _ = probe.shape
+    H, W = obj.shape
+    return Problem(H=H, W=W, N=N, M=M, J=pos.shape[0])
+
+
+def workspace_size(problem: Problem, params) -> int:
+    lib = _abi.load()
+    n = C.c_size_t(0)
+    check(lib.mrpie_workspace_size(C.byref(problem), C.byref(params), C.byref(n)))
+    return n.value
+
+
+def rpie(obj, probe, pos, intens, adam=None, err=None, status=None, workspace=None, stream=None, **params):
+    """Run the M-rPIE sweep in place on (obj, probe[, pos, adam]).
+
+    obj [H, W] complex64, probe [M, N, N] complex64, pos [J, 2] float32,
+    intens [J, N, N] float32 (FFT order), all on the GPU.  Keyword arguments
+    are the fields of mrpie_params.  Returns the workspace tensor used (it
+    can be passed back in to avoid a new allocation).
+    """
+    lib = _abi.load()
+    prm = make_params(**params)
+    pb = problem_of(obj, probe, pos)
+    nbytes = workspace_size(pb, prm)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=obj.device)
+    check(lib.mrpie_rpie(C.byref(pb), C.byref(prm), _dev(obj, torch.complex64, "obj"),
+                         _dev(probe, torch.complex64, "probe"), _dev(pos, torch.float32, "pos"),
+                         _opt(adam, torch.float32, "adam"), _dev(intens, torch.float32, "intens"),
+                         _opt(err, torch.float32, "err"), _opt(status, torch.int32, "status"),
+                         _dev(workspace, torch.uint8, "workspace"), C.c_size_t(workspace.numel()),
+                         _stream(stream)))
+    return workspace
+
+
+def fft2(x, inverse=False, stream=None):
+    """In-place unitary 2-D DFT of x [..., N, N] complex64 (test hook)."""
+    lib = _abi.load()
+    N = x.shape[-1]
+    B = x.numel() // (N * N)
+    check(lib.mrpie_fft2(N, B, _dev(x, torch.complex64, "x"), int(bool(inverse)), _stream(stream)))
+    return x
+
+
+def modulus(psi, intens, stream=None):
+    """In-place modulus replacement (Eq. 7) of psi [M, N, N] by intens [N, N]."""
+    lib = _abi.load()
+    M, N, _ = psi.shape
+    check(lib.mrpie_modulus(N, M, _dev(psi, torch.complex64, "psi"), _dev(intens, torch.float32, "intens"),
+                            _stream(stream)))
+    return psi
+
+
+def validate(problem: Problem, **params) -> int:
+    """Host-only validation; returns the C return code (0 = OK)."""
+    lib = _abi.load()
+    prm = make_params(**params)
+    return lib.mrpie_validate(C.byref(problem), C.byref(prm))
+
+
+TIMED_KERNELS = ("k_rows", "k_cols")
+
+
+def timing_enable(stride: int):
+    """Sample every `stride`-th launch of each timed kernel with HIP events."""
+    check(_abi.load().mrpie_timing_enable(int(stride)))
+
+
+def timing_read():
+    """{kernel: (mean ms, launches timed)} since timing_enable; clears."""
+    n = len(TIMED_KERNELS)
+    avg = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    check(_abi.load().mrpie_timing_read(avg, cnt, n))
+    return {k: (avg[i], cnt[i]) for i, k in enumerate(TIMED_KERNELS)}

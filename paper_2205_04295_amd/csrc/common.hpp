@@ -1,0 +1,134 @@
+// Shared host/device helpers of the mrpie library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "mrpie.h"
+#include "fft.hpp"
+
+namespace mrpie {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define MRPIE_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::mrpie::hip_fail(e_, #call); \
+  } while (0)
+
+inline int n_index(int N) {
+  switch (N) {
+    case 64: return 0;
+    case 128: return 1;
+    case 192: return 2;
+    case 256: return 3;
+    default: return -1;
+  }
+}
+
+// Roots of unity w_N^e = exp(-2 pi i e / N), e < N, for the four sizes;
+// written by k_init_twiddles in double precision and rounded once.  Each
+// translation unit holds its own copy (no relocatable device code).
+static __device__ float2 g_tw[4][256];
+
+static __global__ void k_init_twiddles() {
+  const int idx = blockIdx.x;
+  const int N = idx == 0 ? 64 : idx == 1 ? 128 : idx == 2 ? 192 : 256;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)e / (double)N, &s, &c);
+    g_tw[idx][e] = make_float2((float)c, (float)s);
+  }
+}
+
+static inline int launch_init_twiddles(hipStream_t s) {
+  hipLaunchKernelGGL(k_init_twiddles, dim3(4), dim3(256), 0, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_init_twiddles");
+  return MRPIE_OK;
+}
+
+// Copy the N-entry twiddle table to LDS.
+template <int N>
+__device__ __forceinline__ void load_twiddles(float2* s_tw) {
+  constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : 3;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw[idx][i];
+}
+
+// Workgroup reductions (64-wide waves).
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// red: >= 16 floats of LDS.  All threads get the result.
+__device__ __forceinline__ float block_max(float v, float* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  float r = red[0];
+  for (int i = 1; i < nw; ++i) r = fmaxf(r, red[i]);
+  return r;
+}
+// red: >= 16 doubles of LDS; fixed summation order (deterministic).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += red[i];
+  return r;
+}
+
+__device__ __forceinline__ void flag_status(int* status, int bit) {
+  if (status) atomicOr(status, bit);
+}
+
+// Box corner n = floor(p + 0.5) clamped to [0, lim]; sets the clamp bit.
+__device__ __forceinline__ int box_corner(float p, int lim, int* status) {
+  float q = floorf(p + 0.5f);
+  if (!(q >= 0.0f && q <= (float)lim)) {  // also catches NaN
+    flag_status(status, MRPIE_STATUS_POS_CLAMPED);
+    q = (q > (float)lim) ? (float)lim : 0.0f;
+  }
+  return (int)q;
+}
+
+// XCD-aware unit index: consecutive workgroups are dispatched round-robin
+// over the 8 XCDs; give each XCD a contiguous range of units so that units
+// sharing cache lines share an L2.  Requires nunits % 8 == 0 and
+// gridDim.x == nunits.
+__device__ __forceinline__ int xcd_unit(int b, int nunits) {
+  const int per = nunits >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- timing
+// Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
+// launch of a timed kernel class is bracketed by a HIP event pair on its
+// stream; mrpie_timing_read() averages the recorded durations.
+enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_ADJ = 3, TK_COUNT = 8 };
+struct TimingScope {
+  TimingScope(int kind, hipStream_t s);
+  ~TimingScope();
+  int slot;
+  hipStream_t stream;
+};
+
+}  // namespace mrpie

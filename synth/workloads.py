@@ -141,17 +141,31 @@ def simulate_patterns(rng, O, P, pos, photons, noise=True):
     return I.astype(np.float32), scale
 
 
-def _finish(name, O, P, pos_true, pos0, I, scale, R, params, init_modes=True):
+INIT_PHASE = 0.2
+
+
+def initial_object(seed, H, W):
+    """Initial object guess: unit magnitude with a small white random phase
+    U(-0.2, 0.2) rad (own generator, seed + 1000, so the data draws do not
+    move).  A perfectly flat start would make the first updates depend on
+    the phase of round-off: on a flat object the model spectrum of a smooth
+    probe has near-zero bins where the data are non-zero, and the modulus
+    step keeps the (arbitrary) phase of those bins."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    return np.exp(1j * rng.uniform(-INIT_PHASE, INIT_PHASE, size=(H, W)))
+
+
+def _finish(name, O, P, pos_true, pos0, I, scale, R, params, seed=0):
     M, N, _ = P.shape
     P_true = (P * math.sqrt(scale)).astype(np.complex64)
-    # initial guess: flat object, phase-free probe of the same mode recipe at
-    # the data's mean power
+    # initial guess: near-flat object, phase-free probe of the same mode
+    # recipe at the data's mean power
     P0 = probe_modes(N, R, M, with_phase=False)
     mean_power = float(I.astype(np.float64).sum(axis=(1, 2)).mean())
     P0 = P0 * math.sqrt(mean_power / float(np.sum(np.abs(P0) ** 2)))
     return Workload(name=name, O_true=O.astype(np.complex64), P_true=P_true,
                     pos_true=pos_true.astype(np.float32), I=I,
-                    O0=np.ones(O.shape, dtype=np.complex64),
+                    O0=initial_object(seed, *O.shape).astype(np.complex64),
                     P0=P0.astype(np.complex64), pos0=pos0.astype(np.float32),
                     params=params)
 
@@ -172,7 +186,7 @@ def raster_case(seed=0, H=256, N=64, R=20.0, nside=10, step=16.0, origin=24.0,
     pos = np.floor(raster_scan(rng, nside, step, origin, jitter) + 0.5)
     I, scale = simulate_patterns(rng, O, P, pos, photons, noise)
     return _finish(name, O, P, pos, pos, I, scale, R,
-                   dict(R1_PARAMS, iterations=iterations))
+                   dict(R1_PARAMS, iterations=iterations), seed=seed)
 
 
 def spiral_case(seed=1, H=1024, N=256, M=3, J=1600, R=32.0, c=9.6, photons=1e7,
@@ -196,7 +210,7 @@ def spiral_case(seed=1, H=1024, N=256, M=3, J=1600, R=32.0, c=9.6, photons=1e7,
     if pos_sigma > 0:
         prm.update(subpixel=1, refine=1, refine_start=0, upsample=100, xcorr_norm=1,
                    adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
-    return _finish(name, O, P, true, nominal, I, scale, R, prm)
+    return _finish(name, O, P, true, nominal, I, scale, R, prm, seed=seed)
 
 
 def refine_case(seed=2, **kw):
@@ -214,7 +228,7 @@ def gradient_subset(seed=3, H=128, N=32, M=3, R=10.0, photons=1e6):
     pos = raster_scan(rng, 5, 8.0, 32.0, 0.0)
     pos = pos + rng.uniform(-0.4, 0.4, size=pos.shape)
     I, scale = simulate_patterns(rng, O, P, pos, photons, True)
-    return _finish("grad_subset", O, P, pos, pos, I, scale, R, dict(subpixel=1))
+    return _finish("grad_subset", O, P, pos, pos, I, scale, R, dict(subpixel=1), seed=seed)
 
 
 def batch_jobs(seed=4, njobs=64, sizes=(64, 128, 192, 256), jmin=50, jmax=900,
@@ -238,7 +252,7 @@ def batch_jobs(seed=4, njobs=64, sizes=(64, 128, 192, 256), jmin=50, jmax=900,
         pos = np.clip(np.floor(fermat_spiral(J, c, (span / 2.0, span / 2.0)) + 0.5), 0, span)
         I, scale = simulate_patterns(rng, O, P, pos, photons, True)
         jobs.append(_finish(f"job{b}", O, P, pos, pos, I, scale, R,
-                            dict(R1_PARAMS, iterations=iterations)))
+                            dict(R1_PARAMS, iterations=iterations), seed=seed * 1000 + b))
     return jobs
 
 
@@ -265,4 +279,4 @@ def small_case(seed, H, N, M, J, R=None, photons=1e6, subpixel=False, edges=True
     pos = np.clip(pos, 0, span)
     I, scale = simulate_patterns(rng, O, P, pos, photons, True)
     return _finish(name, O, P, pos, pos, I, scale, R,
-                   dict(R1_PARAMS, subpixel=int(subpixel)))
+                   dict(R1_PARAMS, subpixel=int(subpixel)), seed=seed)

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/mrpie.h declares, and validates problems on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2205_04295_amd import _abi
+from paper_2205_04295_amd._abi import Problem, make_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mrpie.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrpie_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("libmrpie.so is not built (run __graft_entry__.build())")
+    return _abi.load()
+
+
+def test_header_symbols_exported(lib):
+    names = header_functions()
+    assert len(names) >= 6
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.exported_symbols(), f"{n} has no ctypes signature"
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.mrpie_version()
+
+
+def _validate(lib, pb, **kw):
+    return lib.mrpie_validate(C.byref(pb), C.byref(make_params(**kw)))
+
+
+def test_validate_accepts_supported_shapes(lib):
+    for N in (64, 128, 192, 256):
+        for M in (1, 3, 8):
+            assert _validate(lib, Problem(H=N + 7, W=2 * N, N=N, M=M, J=5)) == 0
+
+
+@pytest.mark.parametrize("pb,kw,code", [
+    (Problem(256, 256, 96, 1, 10), {}, _abi.MRPIE_EUNSUPPORTED),
+    (Problem(256, 256, 64, 9, 10), {}, _abi.MRPIE_EUNSUPPORTED),
+    (Problem(256, 256, 64, 0, 10), {}, _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 0), {}, _abi.MRPIE_EINVAL),
+    (Problem(63, 256, 64, 1, 10), {}, _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(beta=1.5), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(gamma=-0.1), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(iterations=-1), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(alpha_obj=float("nan")), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(subpixel=2), _abi.MRPIE_EINVAL),
+])
+def test_validate_rejects(lib, pb, kw, code):
+    assert _validate(lib, pb, **kw) == code
+    assert lib.mrpie_last_error() != b""
+
+
+def test_null_arguments_rejected_before_launch(lib):
+    pb = Problem(256, 256, 64, 1, 10)
+    prm = make_params()
+    assert lib.mrpie_validate(None, C.byref(prm)) == _abi.MRPIE_EINVAL
+    n = C.c_size_t(0)
+    assert lib.mrpie_workspace_size(C.byref(pb), C.byref(prm), C.byref(n)) == 0 and n.value > 0
+    # null arrays are rejected on the host, nothing is launched
+    rc = lib.mrpie_rpie(C.byref(pb), C.byref(prm), None, None, None, None, None, None, None, None,
+                        C.c_size_t(0), None)
+    assert rc == _abi.MRPIE_EINVAL
+    assert lib.mrpie_fft2(96, 1, None, 0, None) == _abi.MRPIE_EUNSUPPORTED
+    assert lib.mrpie_fft2(64, 0, None, 0, None) == 0     # empty batch: nothing to do
+
+
+def test_workspace_too_small_rejected(lib):
+    pb = Problem(256, 256, 64, 1, 10)
+    prm = make_params()
+    fake = C.c_void_p(0x1000)
+    rc = lib.mrpie_rpie(C.byref(pb), C.byref(prm), fake, fake, fake, None, fake, None, None, fake,
+                        C.c_size_t(16), None)
+    assert rc == _abi.MRPIE_EWORKSPACE
