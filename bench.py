@@ -35,6 +35,8 @@ def parse():
                     help="sample every n-th launch of each kernel with HIP events")
     ap.add_argument("--cpu-positions", type=int, default=400,
                     help="positions in the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="independent 256^2 x 3 reconstructions in the batched measurement (0 = skip)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -60,6 +62,43 @@ def cpu_baseline(w, npos):
     return dict(value=npos / dt, unit="positions*iter/s", cores=1, kind="oracle",
                 sample=f"first {npos} of 1600 positions, 1 iteration, FP64 numpy, 1 thread",
                 seconds=round(dt, 3))
+
+
+def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_b, cols_b):
+    """B independent reconstructions of the same shape (each its own object,
+    probe, workspace and a rotated copy of the scan and patterns), advanced
+    lock-step in shared launches; aggregate positions x iterations / s."""
+    B = args.batch
+    J = pos0.shape[0]
+    jobs = []
+    for b in range(B):
+        sh = (b * J) // B
+        jobs.append(dict(obj=obj0.clone(), probe=probe0.clone(),
+                         pos=torch.roll(pos0, sh, 0).contiguous(), intens=torch.roll(I0, sh, 0).contiguous()))
+    for it in range(args.warmup):
+        wss = api.rpie_batched(jobs, iterations=1, iter_offset=it, **prm)
+        for j, ws in zip(jobs, wss):
+            j["workspace"] = ws
+    torch.cuda.synchronize()
+    api.timing_enable(args.timing_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        api.rpie_batched(jobs, iterations=1, iter_offset=args.warmup + k, **prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = api.timing_read()
+    api.timing_enable(0)
+    per_launch = {"k_rows": rows_b * B, "k_cols": cols_b * B}
+    dom = max(kt, key=lambda k: kt[k][0])
+    ach = per_launch[dom] / (kt[dom][0] * 1e-3) / 1e9 if kt[dom][0] > 0 else 0.0
+    return {"jobs": B, "value": round(B * J * args.steps / el, 1), "unit": "positions*iter/s (aggregate)",
+            "ms_per_step": round(el * 1e3 / args.steps, 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom,
+                         "kernel_avg_us": round(kt[dom][0] * 1e3, 3),
+                         "algorithmic_bytes_per_launch": per_launch[dom]},
+            "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()}}
 
 
 def main():
@@ -116,6 +155,10 @@ def main():
     # whole-path algorithmic bandwidth (all kernels of a step)
     path_gbs = (rows_b + cols_b) * J / (ms_per_step * 1e-3) / 1e9
 
+    batched = None
+    if args.batch > 0:
+        batched = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b)
+
     if args.calib:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -153,6 +196,7 @@ def main():
                      "launches_timed": int(kt[dom][1])},
         "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
         "path_algorithmic_GBs": round(path_gbs, 1),
+        "batched": batched,
         "cpu_baseline": cpu,
         "status": int(status.item()),
         "final_error": float(err.item()),

@@ -127,6 +127,45 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
                float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);
 
+/* One reconstruction of a batch: its shape, its arrays (device memory, as
+ * for mrpie_rpie) and its own workspace (mrpie_workspace_size bytes for its
+ * problem and the shared parameters). */
+typedef struct {
+  mrpie_problem problem;
+  void* obj;            /* [H][W] complex64, in/out */
+  void* probe;          /* [M][N][N] complex64, in/out */
+  float* pos;           /* [J][2] float32, in */
+  const float* intens;  /* [J][N][N] float32, in */
+  float* err_out;       /* [iterations] float32, out (may be NULL) */
+  int32_t* status;      /* int32 status word (may be NULL) */
+  void* ws;
+  size_t ws_bytes;
+} mrpie_job;
+
+/* Batched M-rPIE: runs mrpie_rpie's sweep (same parameters for every job;
+ * refine and subpixel must be 0) on `njobs` independent reconstructions of
+ * any mix of N, M, J and object size, lock-step by position: every launch
+ * advances one position of every unfinished job, so one pair of launches
+ * carries the work of all jobs.  Each job's result is bitwise equal to a
+ * mrpie_rpie call on that job alone.  `jobs` is a HOST array read during
+ * the call. */
+int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
+
+/* Launch shape of the sweep's two passes, per probe size N and call class
+ * (batched = 0: single-job mrpie_rpie; 1: mrpie_rpie_batched with more
+ * than one job).  rows_radix / cols_radix: 4 or 8, the radix of the LDS
+ * Stockham FFT stages of the row / column pass (radix 4: more threads per
+ * transform, shorter latency; radix 8: fewer stages, less LDS traffic);
+ * rows_threads: 256 or 512 threads per row workgroup.  The setting is
+ * process-wide host state; results do not depend on it beyond float
+ * rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
+ * candidates on the device and installs the fastest with mrpie_set_tuning. */
+typedef struct {
+  int32_t rows_radix, cols_radix, rows_threads;
+} mrpie_tuning;
+int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
+int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);
+
 /* Test hook: in-place unitary 2-D DFT (D_z, Eq. 2; inverse = 1 gives
  * D_{-z}) of B contiguous N x N complex64 arrays.  N in {64,128,192,256}. */
 int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream);

@@ -48,6 +48,16 @@ def make_params(**kw) -> Params:
     return Params(**d)
 
 
+class Job(C.Structure):
+    _fields_ = [("problem", Problem), ("obj", C.c_void_p), ("probe", C.c_void_p), ("pos", C.c_void_p),
+                ("intens", C.c_void_p), ("err_out", C.c_void_p), ("status", C.c_void_p),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("rows_radix", C.c_int32), ("cols_radix", C.c_int32), ("rows_threads", C.c_int32)]
+
+
 class MrpieError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"mrpie error {code}: {msg}")
@@ -61,6 +71,9 @@ _SIGS = {
     "mrpie_validate": (C.c_int, [C.POINTER(Problem), C.POINTER(Params)]),
     "mrpie_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_size_t)]),
     "mrpie_rpie": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "mrpie_rpie_batched": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Params), _P]),
+    "mrpie_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "mrpie_get_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "mrpie_fft2": (C.c_int, [C.c_int32, C.c_int32, _P, C.c_int32, _P]),
     "mrpie_modulus": (C.c_int, [C.c_int32, C.c_int32, _P, _P, _P]),
     "mrpie_timing_enable": (C.c_int, [C.c_int32]),

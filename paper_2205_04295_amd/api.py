@@ -71,6 +71,31 @@ def rpie(obj, probe, pos, intens, adam=None, err=None, status=None, workspace=No
     return workspace
 
 
+def rpie_batched(jobs, stream=None, **params):
+    """Run independent M-rPIE reconstructions lock-step in shared launches.
+
+    jobs: list of dicts with GPU tensors obj, probe, pos, intens and optional
+    err, status, workspace.  Keyword arguments are the shared mrpie_params.
+    Returns the list of workspaces used."""
+    lib = _abi.load()
+    prm = make_params(**params)
+    arr = (_abi.Job * len(jobs))()
+    keep = []
+    for b, j in enumerate(jobs):
+        pb = problem_of(j["obj"], j["probe"], j["pos"])
+        nbytes = workspace_size(pb, prm)
+        ws = j.get("workspace")
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=j["obj"].device)
+        keep.append(ws)
+        arr[b] = _abi.Job(pb, _dev(j["obj"], torch.complex64, "obj"), _dev(j["probe"], torch.complex64, "probe"),
+                          _dev(j["pos"], torch.float32, "pos"), _dev(j["intens"], torch.float32, "intens"),
+                          _opt(j.get("err"), torch.float32, "err"), _opt(j.get("status"), torch.int32, "status"),
+                          _dev(ws, torch.uint8, "workspace"), C.c_size_t(ws.numel()))
+    check(lib.mrpie_rpie_batched(len(jobs), C.cast(arr, C.c_void_p), C.byref(prm), _stream(stream)))
+    return keep
+
+
 def fft2(x, inverse=False, stream=None):
     """In-place unitary 2-D DFT of x [..., N, N] complex64 (test hook)."""
     lib = _abi.load()

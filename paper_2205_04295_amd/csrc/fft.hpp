@@ -13,6 +13,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace mrpie {
 
 struct c32 {
@@ -99,12 +101,20 @@ __device__ __forceinline__ void dftR(float2* v) {
   else dft2<INV>(v[0], v[1]);
 }
 
-// Stage plans (radix per stage, first to last).
-template <int N> struct Plan;
-template <> struct Plan<64>  { static constexpr int S = 2; static constexpr int R[4] = {8, 8, 1, 1}; };
-template <> struct Plan<128> { static constexpr int S = 3; static constexpr int R[4] = {8, 4, 4, 1}; };
-template <> struct Plan<192> { static constexpr int S = 3; static constexpr int R[4] = {8, 8, 3, 1}; };
-template <> struct Plan<256> { static constexpr int S = 3; static constexpr int R[4] = {8, 8, 4, 1}; };
+// Stage plans (radix per stage, first to last; 1 = no stage).
+//   Plan8: fewest stages (radix 8), for throughput-bound batches.
+//   Plan4: radix 4 (+2 / 3), twice the threads per transform and half the
+//          work per thread and stage: shorter latency for small batches.
+template <int N> struct Plan8;
+template <> struct Plan8<64>  { static constexpr int R[4] = {8, 8, 1, 1}; };
+template <> struct Plan8<128> { static constexpr int R[4] = {8, 4, 4, 1}; };
+template <> struct Plan8<192> { static constexpr int R[4] = {8, 8, 3, 1}; };
+template <> struct Plan8<256> { static constexpr int R[4] = {8, 8, 4, 1}; };
+template <int N> struct Plan4;
+template <> struct Plan4<64>  { static constexpr int R[4] = {4, 4, 4, 1}; };
+template <> struct Plan4<128> { static constexpr int R[4] = {4, 4, 4, 2}; };
+template <> struct Plan4<192> { static constexpr int R[4] = {4, 4, 4, 3}; };
+template <> struct Plan4<256> { static constexpr int R[4] = {4, 4, 4, 4}; };
 
 // One Stockham stage over `nb` transforms of length N stored contiguously
 // (transform t at src + t*N).  tw: N-th roots w_N^e = exp(-2 pi i e / N).
@@ -140,19 +150,23 @@ __device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __
 
 // Full N-point transforms of `nb` contiguous rows in LDS buffer `a`, using
 // `b` as the ping-pong partner.  Returns the buffer holding the result.
-// Callers must __syncthreads() before (data ready) — the result is ready on
+// Callers must __syncthreads() before (data ready); the result is ready on
 // return (a barrier ends every stage).
-template <int N, bool INV>
+template <int N, bool INV, bool R4 = true>
 __device__ float2* fft_lds(float2* a, float2* b, int nb, const float2* __restrict__ tw) {
-  constexpr int R0 = Plan<N>::R[0], R1 = Plan<N>::R[1], R2 = Plan<N>::R[2];
+  using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
   stage<N, R0, 1, INV>(a, b, nb, tw);
   __syncthreads();
   stage<N, R1, R0, INV>(b, a, nb, tw);
   __syncthreads();
-  if constexpr (Plan<N>::S == 2) return a;
+  if constexpr (R2 == 1) return a;
   stage<N, R2, R0 * R1, INV>(a, b, nb, tw);
   __syncthreads();
-  return b;
+  if constexpr (R3 == 1) return b;
+  stage<N, R3, R0 * R1 * R2, INV>(b, a, nb, tw);
+  __syncthreads();
+  return a;
 }
 
 }  // namespace mrpie

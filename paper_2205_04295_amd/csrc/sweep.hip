@@ -2,94 +2,83 @@
 // Eq. 4-7).
 //
 // A position step is split at the two transposes of the 2-D FFT into two
-// launches; kernel boundaries are the device-wide sync points (a graph-
-// replayed launch costs less on MI355X than a cross-XCD grid barrier):
+// launches; kernel boundaries are the device-wide sync points (on MI355X a
+// graph-replayed launch costs less than a cross-XCD grid barrier):
 //
-//   k_cols  (step s):   per column stripe, all modes: forward column FFT,
-//                       mode-summed modulus replacement (Eq. 7), inverse
-//                       column FFT, in place in psi[s&1]; accumulates the
-//                       Fourier error.
-//   k_rows  (s-1 -> s): per probe row r: inverse row FFTs of psi[(s-1)&1],
-//                       probe update of row r (Eq. 5) and object update of
-//                       the box rows that become rows of the next box or
-//                       leave it (Eq. 6), then gather of row r of the next
+//   k_cols  (step s):   one workgroup per detector column, all modes:
+//                       forward column FFT, mode-summed modulus replacement
+//                       (Eq. 7), inverse column FFT, in place in psi[s&1];
+//                       accumulates the Fourier error.
+//   k_rows  (s-1 -> s): one workgroup per probe row r: inverse row FFTs of
+//                       psi[(s-1)&1]; probe update of row r (Eq. 5); object
+//                       update (Eq. 6) of the box rows that are rows of the
+//                       next box or leave it; gather of row r of the next
 //                       box, exit waves P_p o (Eq. 1/4) and forward row FFTs
 //                       into psi[s&1].
 //
 // Probe, patch and spectra are double-buffered by step parity, so inside a
-// k_rows launch every buffer a unit reads is disjoint from every buffer any
-// unit writes; the object rows a unit writes are exactly the rows it then
-// re-gathers (it merges them from LDS), so the sweep needs no atomics and is
-// bitwise deterministic.  The O update of step s-1 and the gather of step s
-// happen in one launch, which keeps rPIE's order: position s reads the
-// object after position s-1 has been written.
+// k_rows launch every buffer a workgroup reads is disjoint from every buffer
+// any workgroup writes; the object rows a workgroup writes are exactly the
+// rows it then re-gathers (merged from LDS).  The sweep has no atomics on
+// data and is bitwise deterministic.  The object update of step s-1 and the
+// gather of step s are one launch, which keeps rPIE's order: position s
+// reads the object after position s-1 has written it.
+//
+// Batching: blockIdx.y selects a job from the launch's job table; every job
+// advances one position per launch pair (lock-step), so many independent
+// reconstructions of different N, M, J fill the GPU that one sweep cannot.
+// Every global load a workgroup needs is issued at kernel start, before the
+// first LDS stage, so each launch pays one memory latency.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
-#include "common.hpp"
+#include "sweep.hpp"
 
 namespace mrpie {
 
-enum RowMode { ROWS_HEAD = 0, ROWS_MID = 1, ROWS_TAIL = 2 };
+// select one of a pair without dynamic indexing (keeps the layout in SGPRs)
+__device__ __forceinline__ size_t pick(const size_t (&a)[2], int i) { return i ? a[1] : a[0]; }
 
-struct SweepArgs {
-  int H, W, N, M, J, T;
-  float alpha_obj, alpha_probe, beta, gamma;
-  int iter_offset, probe_update_start;
-  float2* obj;
-  float2* probe[2];   // probe[s&1] is the probe used at step s
-  const float* pos;   // [J][2]
-  const float* I;     // [J][N][N]
-  float2* psi[2];     // [M][N][N]
-  float2* patch[2];   // [N][N]
-  float* pmax[2];     // [N] per-row max of sum_p |P_p|^2 of probe[s&1]
-  float* omax[2];     // [N] per-row max of |o_s|^2
-  int* box[2];        // [2] integer corner of the box gathered at step s
-  double* err_acc;    // [T][kErrSlots]
-  int* status;
-  const int* iter_dev;  // iteration counter (relative to the call)
-};
-
-constexpr int kErrSlots = 256;
-constexpr int kCols = 2;  // columns per k_cols workgroup
-
-// ---------------------------------------------------------------- k_rows
-template <int N>
-__global__ __launch_bounds__(256) void k_rows(SweepArgs a, int jn, int mode) {
-  extern __shared__ float2 smem[];
-  const int M = a.M;
-  float2* tw = smem;                 // N
-  float2* pn = tw + N;               // M*N  new probe row r
-  float2* orow = pn + M * N;         // N    updated object row (box-prev row rb1)
-  float2* bufA = orow + N;           // 3*M*N
-  float2* bufB = bufA + 3 * M * N;   // 3*M*N
-  __shared__ float redf[16];
-  __shared__ float s_omax, s_pmax;
-
+template <int N, bool R4>
+__device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
   const int r = blockIdx.x;
-  const int it = *a.iter_dev;
-  const int s = it * a.J + jn;
-  const bool has_prev = mode != ROWS_HEAD;
-  const bool has_next = mode != ROWS_TAIL;
-  const int cur = s & 1, prv = (s - 1) & 1;
+  if (t > total || r >= N) return;
+  const bool has_prev = t > 0, has_next = t < total;
+  const int cur = t & 1, prv = (t + 1) & 1;
+  const int jn = has_next ? t % jb.J : 0;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  char* ws = jb.ws;
   const size_t NN = (size_t)N * N;
+  const int tid = threadIdx.x;
+  const bool lane = tid < N;  // this thread owns column `tid`
 
-  load_twiddles<N>(tw);
+  float2* tw = smem;               // N
+  float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
+  float2* bufA = orow + N;         // 3*M*N
+  float2* bufB = bufA + 3 * M * N; // 3*M*N
+  __shared__ float redf[16];
 
-  // next box corner from the current position estimate
+  const float2* psi_prev = (const float2*)(ws + pick(L.psi, prv));
+  const float2* patch_prev = (const float2*)(ws + pick(L.patch, prv));
+  const float2* Pold = prv == 0 ? jb.probe : (const float2*)(ws + L.probe1);
+  float2* Pnew = cur == 0 ? jb.probe : (float2*)(ws + L.probe1);
+  int* box_prev = (int*)(ws + pick(L.box, prv));
+  int* box_cur = (int*)(ws + pick(L.box, cur));
+
+  // ---- box geometry
   int ny_n = 0, nx_n = 0;
   if (has_next) {
-    ny_n = box_corner(a.pos[2 * jn], a.H - N, a.status);
-    nx_n = box_corner(a.pos[2 * jn + 1], a.W - N, a.status);
-    if (r == 0 && threadIdx.x == 0) {
-      a.box[cur][0] = ny_n;
-      a.box[cur][1] = nx_n;
-    }
+    ny_n = box_corner(jb.pos[2 * jn], jb.H - N, jb.status);
+    nx_n = box_corner(jb.pos[2 * jn + 1], jb.W - N, jb.status);
   }
   int ny_p = 0, nx_p = 0, rb1 = -1, rb2 = -1;
   if (has_prev) {
-    ny_p = a.box[prv][0];
-    nx_p = a.box[prv][1];
+    ny_p = box_prev[0];
+    nx_p = box_prev[1];
     if (has_next) {
       const int dy = ny_n - ny_p;
       if (r + dy >= 0 && r + dy < N) rb1 = r + dy;
@@ -99,290 +88,385 @@ __global__ __launch_bounds__(256) void k_rows(SweepArgs a, int jn, int mode) {
       rb1 = r;
     }
   }
+  // distinct box rows needing an inverse row FFT: slot 0 is the probe row r
+  const bool u1 = rb1 >= 0 && rb1 != r, u2 = rb2 >= 0 && rb2 != r;
+  const int rows[3] = {r, u1 ? rb1 : rb2, rb2};
+  const int ns = has_prev ? 1 + (int)u1 + (int)u2 : 0;
 
-  float* pmax_out = a.pmax[cur];
+  // ---- issue every global load up front
+  float2 pv[3][MM];      // psi_prev rows (row-transformed spectra)
+  float2 Pq[3][MM];      // old probe at the slot rows
+  float2 oq[3];          // old patch at the slot rows
+  float2 og = make_float2(0.f, 0.f);  // object value of the next box row, outside the updated row
+  float2 Ph[MM];         // probe row r when there is no previous step
+  float om_in = 0.f, pm_in = 0.f;
+  const int c = tid;
+  if (lane) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q >= ns) break;
+      const size_t off = (size_t)rows[q] * N + c;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          pv[q][p] = psi_prev[p * NN + off];
+          Pq[q][p] = Pold[p * NN + off];
+        }
+      oq[q] = patch_prev[off];
+    }
+    if (has_prev) {
+      om_in = ((const float*)(ws + pick(L.omax, prv)))[c];
+      pm_in = ((const float*)(ws + pick(L.pmax, prv)))[c];
+    } else {
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) Ph[p] = Pnew[p * NN + (size_t)r * N + c];
+    }
+    if (has_next) {
+      const int gx = nx_n + c;
+      const bool merged = rb1 >= 0 && gx >= nx_p && gx < nx_p + N;
+      if (!merged) og = jb.obj[(size_t)(ny_n + r) * jb.W + gx];
+    }
+  }
+  if (has_next && r == 0 && tid == 0) {
+    box_cur[0] = ny_n;
+    box_cur[1] = nx_n;
+  }
+  load_twiddles<N>(tw);
+
+  float2 Pn[MM];
+  bool bad = false;
   if (has_prev) {
-    // ---- reductions of the previous step's max terms
-    float vo = 0.f, vp = 0.f;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-      vo = fmaxf(vo, a.omax[prv][i]);
-      vp = fmaxf(vp, a.pmax[prv][i]);
-    }
-    vo = block_max(vo, redf);
-    vp = block_max(vp, redf + 8);
-    if (threadIdx.x == 0) {
-      s_omax = vo;
-      s_pmax = vp;
-    }
-    // distinct rows needing an inverse row FFT: slot 0 = probe row r,
-    // slot 1 = rb1, slot 2 = rb2 (slots equal to r are served by slot 0)
-    const int nsl = 3;
-    const float2* src = a.psi[prv];
-    for (int i = threadIdx.x; i < nsl * M * N; i += blockDim.x) {
-      const int sl = i / (M * N);
-      const int rem = i - sl * M * N;
-      const int p = rem / N, c = rem - p * N;
-      const int row = sl == 0 ? r : (sl == 1 ? rb1 : rb2);
-      if (row >= 0 && (sl == 0 || row != r)) bufA[i] = src[p * NN + (size_t)row * N + c];
-      else bufA[i] = make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    float2* res = fft_lds<N, true>(bufA, bufB, nsl * M, tw);
-    const float omax = s_omax, pmaxv = s_pmax;
-
-    // ---- probe update of row r (Eq. 5), from the pre-update o and P
-    const int it_abs = a.iter_offset + (s - 1) / a.J;
-    const bool upd_p = it_abs >= a.probe_update_start;
-    const float2* Pold = a.probe[prv];
-    float2* Pnew = a.probe[cur];
-    const float2* patch = a.patch[prv];
-    float pm = 0.f;
-    bool bad = false;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const float2 o = patch[(size_t)r * N + c];
-      const float o2 = cabs2(o);
-      const float dP = a.beta * omax + (1.f - a.beta) * o2;
-      const float g = (upd_p && dP != 0.f) ? a.alpha_probe / dP : 0.f;
-      float ps = 0.f;
-      for (int p = 0; p < M; ++p) {
-        const float2 P = Pold[p * NN + (size_t)r * N + c];
-        const float2 d = csub(res[p * N + c], cmul(P, o));
-        const float2 Pn = cadd(P, cscale(cmulc(d, o), g));
-        pn[p * N + c] = Pn;
-        Pnew[p * NN + (size_t)r * N + c] = Pn;
-        ps += cabs2(Pn);
+    if (lane) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (q >= ns) break;
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) bufA[(q * M + p) * N + c] = pv[q][p];
       }
+    }
+    const float omax = block_max(om_in, redf);
+    const float pmaxv = block_max(pm_in, redf + 8);  // (contains the barrier before the FFT)
+    float2* res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
+
+    // ---- probe update of row r (Eq. 5) from the pre-update o and P
+    const int it_abs = cm.iter_offset + (t - 1) / jb.J;
+    const bool upd_p = it_abs >= cm.probe_update_start;
+    float pm = 0.f;
+    if (lane) {
+      const float2 o = oq[0];
+      const float o2 = cabs2(o);
+      const float dP = cm.beta * omax + (1.f - cm.beta) * o2;
+      const float g = (upd_p && dP != 0.f) ? cm.alpha_probe / dP : 0.f;
+      float ps = 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          const float2 P = Pq[0][p];
+          const float2 d = csub(res[p * N + c], cmul(P, o));
+          Pn[p] = cadd(P, cscale(cmulc(d, o), g));
+          Pnew[p * NN + (size_t)r * N + c] = Pn[p];
+          ps += cabs2(Pn[p]);
+        }
       bad |= !isfinite(ps);
-      pm = fmaxf(pm, ps);
+      pm = ps;
     }
     pm = block_max(pm, redf);
-    if (threadIdx.x == 0) pmax_out[r] = pm;
+    if (tid == 0) ((float*)(ws + pick(L.pmax, cur)))[r] = pm;
 
-    // ---- object update (Eq. 6) of box rows rb1 / rb2
-    for (int slot = 1; slot <= 2; ++slot) {
-      const int rb = slot == 1 ? rb1 : rb2;
-      if (rb < 0) continue;
-      const int bs = (rb == r) ? 0 : slot;
-      const float2* dres = res + bs * M * N;
-      float2* orow_g = a.obj + (size_t)(ny_p + rb) * a.W + nx_p;
-      for (int c = threadIdx.x; c < N; c += blockDim.x) {
-        const float2 o = patch[(size_t)rb * N + c];
+    // ---- object update (Eq. 6) of box rows rb1 / rb2: slot 0 when one of
+    //      them is the probe row r, slots 1.. otherwise
+    if (lane) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const bool is_obj = q == 0 ? (rb1 == r || rb2 == r) : (q < ns);
+        if (!is_obj) continue;
+        const int rb = rows[q];
+        const float2 o = oq[q];
         float Ps = 0.f;
         float2 num = make_float2(0.f, 0.f);
-        for (int p = 0; p < M; ++p) {
-          const float2 P = Pold[p * NN + (size_t)rb * N + c];
-          const float2 d = csub(dres[p * N + c], cmul(P, o));
-          num = cadd(num, cmulc(d, P));
-          Ps += cabs2(P);
-        }
-        const float dO = a.gamma * pmaxv + (1.f - a.gamma) * Ps;
-        const float g = dO != 0.f ? a.alpha_obj / dO : 0.f;
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) {
+            const float2 P = Pq[q][p];
+            const float2 d = csub(res[(q * M + p) * N + c], cmul(P, o));
+            num = cadd(num, cmulc(d, P));
+            Ps += cabs2(P);
+          }
+        const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
+        const float g = dO != 0.f ? cm.alpha_obj / dO : 0.f;
         const float2 on = cadd(o, cscale(num, g));
         bad |= !(isfinite(on.x) && isfinite(on.y));
-        orow_g[c] = on;
-        if (slot == 1) orow[c] = on;
+        jb.obj[(size_t)(ny_p + rb) * jb.W + nx_p + c] = on;
+        if (rb == rb1) orow[c] = on;
       }
     }
-    if (bad) flag_status(a.status, MRPIE_STATUS_NONFINITE);
+    if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
     __syncthreads();
+  } else {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) Pn[p] = Ph[p];
   }
 
   if (!has_next) return;
 
-  // ---- gather row r of the next box, merging the row just updated
-  const int gy = ny_n + r;
-  const float2* grow = a.obj + (size_t)gy * a.W;
-  float2* patch_n = a.patch[cur];
-  const float2* Pcur = a.probe[cur];
+  // ---- gather row r of the next box (merging the row just updated),
+  //      exit waves and forward row FFTs
   float om = 0.f, pm0 = 0.f;
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+  if (lane) {
     const int gx = nx_n + c;
-    float2 o;
-    if (rb1 >= 0 && gx >= nx_p && gx < nx_p + N) o = orow[gx - nx_p];
-    else o = grow[gx];
-    patch_n[(size_t)r * N + c] = o;
-    om = fmaxf(om, cabs2(o));
+    const float2 o = (rb1 >= 0 && gx >= nx_p && gx < nx_p + N) ? orow[gx - nx_p] : og;
+    ((float2*)(ws + pick(L.patch, cur)))[(size_t)r * N + c] = o;
+    om = cabs2(o);
     float ps = 0.f;
-    for (int p = 0; p < M; ++p) {
-      const float2 P = has_prev ? pn[p * N + c] : Pcur[p * NN + (size_t)r * N + c];
-      ps += cabs2(P);
-      bufA[p * N + c] = cmul(P, o);
-    }
-    pm0 = fmaxf(pm0, ps);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        ps += cabs2(Pn[p]);
+        bufA[p * N + c] = cmul(Pn[p], o);
+      }
+    pm0 = ps;
   }
   om = block_max(om, redf);
   if (!has_prev) pm0 = block_max(pm0, redf + 8);
-  if (threadIdx.x == 0) {
-    a.omax[cur][r] = om;
-    if (!has_prev) pmax_out[r] = pm0;
+  if (tid == 0) {
+    ((float*)(ws + pick(L.omax, cur)))[r] = om;
+    if (!has_prev) ((float*)(ws + pick(L.pmax, cur)))[r] = pm0;
   }
   __syncthreads();
-  float2* res = fft_lds<N, false>(bufA, bufB, M, tw);
-  float2* dst = a.psi[cur];
-  for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
-    const int p = i / N, c = i - p * N;
-    dst[p * NN + (size_t)r * N + c] = res[i];
+  float2* res = fft_lds<N, false, R4>(bufA, bufB, M, tw);
+  float2* dst = (float2*)(ws + pick(L.psi, cur));
+  for (int i = tid; i < M * N; i += blockDim.x) {
+    const int p = i / N, cc = i - p * N;
+    dst[p * NN + (size_t)r * N + cc] = res[i];
   }
 }
 
-// ---------------------------------------------------------------- k_cols
-template <int N, int WC>
-__global__ __launch_bounds__(256) void k_cols(SweepArgs a, int jn) {
-  extern __shared__ float2 smem[];
-  const int M = a.M;
+template <int N, bool R4>
+__device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
+  if (t >= total) return;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);  // column of this workgroup
+  if (u >= N) return;
+  const int it = t / jb.J, jn = t - it * jb.J;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  const size_t NN = (size_t)N * N;
+  float2* psi = (float2*)(jb.ws + pick(L.psi, t & 1));
+  const int k = threadIdx.x;
+  const bool lane = k < N;
+
   float2* tw = smem;
   float2* bufA = tw + N;
-  float2* bufB = bufA + M * WC * N;
+  float2* bufB = bufA + M * N;
   __shared__ double redd[16];
-  const int it = *a.iter_dev;
-  const int s = it * a.J + jn;
-  const size_t NN = (size_t)N * N;
-  const int nunits = N / WC;
-  const int u = xcd_unit(blockIdx.x, nunits);
-  const int c0 = u * WC;
-  float2* psi = a.psi[s & 1];
-  const float* I = a.I + (size_t)jn * NN;
 
+  double* err_slot = (double*)(jb.ws + L.err) + (size_t)it * kErrSlots + u;
+  const double err_old = threadIdx.x == 0 ? *err_slot : 0.0;
+  float Iv = 0.f;
+  float2 v[MM];
+  if (lane) {
+    Iv = jb.I[(size_t)jn * NN + (size_t)k * N + u];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) v[p] = psi[p * NN + (size_t)k * N + u];
+  }
   load_twiddles<N>(tw);
-  for (int i = threadIdx.x; i < M * N * WC; i += blockDim.x) {
-    const int p = i / (N * WC);
-    const int rem = i - p * N * WC;
-    const int k = rem / WC, cc = rem - k * WC;
-    bufA[(p * WC + cc) * N + k] = psi[p * NN + (size_t)k * N + c0 + cc];
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) bufA[p * N + k] = v[p];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false>(bufA, bufB, M * WC, tw);
+  float2* F = fft_lds<N, false, R4>(bufA, bufB, M, tw);
   float2* G = (F == bufA) ? bufB : bufA;
-  // modulus replacement, Eq. 7; the 2-D transform here is unnormalised
-  // (N x unitary) and the inverse will be too, so the factor carries 1/N.
+  // Eq. 7: the 2-D transform here is unnormalised (N x unitary) and so is
+  // the inverse, so the scale factor carries one 1/N.
   const float invN = 1.0f / (float)N;
   double e = 0.0;
-  bool bad = false;
-  for (int i = threadIdx.x; i < N * WC; i += blockDim.x) {
-    const int k = i / WC, cc = i - k * WC;
+  if (lane) {
     float S = 0.f;
-    for (int p = 0; p < M; ++p) S += cabs2(F[(p * WC + cc) * N + k]);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) S += cabs2(F[p * N + k]);
     const float Au = sqrtf(S);
-    const float sq = sqrtf(fmaxf(I[(size_t)k * N + c0 + cc], 0.f));
+    const float sq = sqrtf(fmaxf(Iv, 0.f));
     const float d = Au * invN - sq;
-    e += (double)d * (double)d;
-    bad |= !isfinite(S);
+    e = (double)d * (double)d;
+    if (!isfinite(S)) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
     const float f = S > 0.f ? sq / Au * invN : 0.f;
-    for (int p = 0; p < M; ++p) G[(p * WC + cc) * N + k] = cscale(F[(p * WC + cc) * N + k], f);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) G[p * N + k] = cscale(F[p * N + k], f);
   }
-  if (bad) flag_status(a.status, MRPIE_STATUS_NONFINITE);
   __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, M * WC, tw);
-  for (int i = threadIdx.x; i < M * N * WC; i += blockDim.x) {
-    const int p = i / (N * WC);
-    const int rem = i - p * N * WC;
-    const int k = rem / WC, cc = rem - k * WC;
-    psi[p * NN + (size_t)k * N + c0 + cc] = H[(p * WC + cc) * N + k];
+  float2* H = fft_lds<N, true, R4>(G, F, M, tw);
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) psi[p * NN + (size_t)k * N + u] = H[p * N + k];
   }
   e = block_sum(e, redd);
-  if (threadIdx.x == 0) a.err_acc[(size_t)it * kErrSlots + u] += e;
+  if (threadIdx.x == 0) *err_slot = err_old + e;
+}
+
+template <bool R4>
+__global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
+  extern __shared__ float2 smem[];
+  const JobRec& jb = a.job[blockIdx.y];
+  switch (jb.N) {
+    case 64: rows_body<64, R4>(a.c, jb, t, smem); break;
+    case 128: rows_body<128, R4>(a.c, jb, t, smem); break;
+    case 192: rows_body<192, R4>(a.c, jb, t, smem); break;
+    default: rows_body<256, R4>(a.c, jb, t, smem); break;
+  }
+}
+
+template <bool R4>
+__global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
+  extern __shared__ float2 smem[];
+  const JobRec& jb = a.job[blockIdx.y];
+  switch (jb.N) {
+    case 64: cols_body<64, R4>(jb, t, smem); break;
+    case 128: cols_body<128, R4>(jb, t, smem); break;
+    case 192: cols_body<192, R4>(jb, t, smem); break;
+    default: cols_body<256, R4>(jb, t, smem); break;
+  }
 }
 
 // ------------------------------------------------------- small kernels
-__global__ void k_zero_words(int* p, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+__global__ void k_zero_err(const LaunchArgs a) {
+  const JobRec& jb = a.job[blockIdx.y];
+  const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
+  double* e = (double*)(jb.ws + L.err);
+  const size_t n = (size_t)(jb.T > 0 ? jb.T : 1) * kErrSlots;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) e[i] = 0.0;
 }
-__global__ void k_advance(int* iter_dev) {
-  if (threadIdx.x == 0) *iter_dev += 1;
-}
-// per-block partial sums of max(I, 0), fixed order
-__global__ __launch_bounds__(256) void k_isum_partial(const float* I, size_t n, double* part) {
+
+// per-job partial sums of max(I, 0), fixed order (blockIdx.x = part)
+__global__ __launch_bounds__(256) void k_isum_partial(const LaunchArgs a) {
   __shared__ double red[16];
+  const JobRec& jb = a.job[blockIdx.y];
+  const size_t n = (size_t)jb.J * jb.N * jb.N;
   double v = 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    v += (double)fmaxf(I[i], 0.f);
+    v += (double)fmaxf(jb.I[i], 0.f);
   v = block_sum(v, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
-}
-__global__ __launch_bounds__(256) void k_finalize_err(const double* err_acc, const double* part, int nparts,
-                                                     int T, float* err_out) {
-  __shared__ double red[16];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[i];
-  const double isum = block_sum(v, red);
-  for (int t = 0; t < T; ++t) {
-    double e = 0.0;
-    for (int i = threadIdx.x; i < kErrSlots; i += blockDim.x) e += err_acc[(size_t)t * kErrSlots + i];
-    e = block_sum(e, red);
-    if (threadIdx.x == 0) err_out[t] = (float)(isum > 0.0 ? e / isum : e);
-  }
-}
-__global__ void k_copy(float2* dst, const float2* src, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
+  const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
+  if (threadIdx.x == 0) ((double*)(jb.ws + L.isum))[blockIdx.x] = v;
 }
 
-// ------------------------------------------------------------ host side
-constexpr int kIsumParts = 1024;
-
-struct SweepLayout {
-  size_t psi[2], patch[2], probe1, pmax[2], omax[2], box[2], err, isum, iter, total;
+struct ErrOut {
+  float* p[kMaxJobsPerLaunch];
 };
 
-static SweepLayout sweep_layout(const mrpie_problem* pb, const mrpie_params* pr) {
-  SweepLayout L{};
-  const size_t NN = (size_t)pb->N * pb->N;
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-  for (int i = 0; i < 2; ++i) L.psi[i] = take(pb->M * NN * 8);
-  for (int i = 0; i < 2; ++i) L.patch[i] = take(NN * 8);
-  L.probe1 = take(pb->M * NN * 8);
-  for (int i = 0; i < 2; ++i) L.pmax[i] = take(pb->N * 4);
-  for (int i = 0; i < 2; ++i) L.omax[i] = take(pb->N * 4);
-  for (int i = 0; i < 2; ++i) L.box[i] = take(16);
-  L.err = take((size_t)std::max(pr->iterations, 1) * kErrSlots * 8);
-  L.isum = take(kIsumParts * 8);
-  L.iter = take(16);
-  L.total = off;
-  return L;
+// err_out[it] = sum of the per-column partials / sum of the intensities
+__global__ __launch_bounds__(256) void k_finish(const LaunchArgs a, const ErrOut eo) {
+  __shared__ double red[16];
+  const JobRec& jb = a.job[blockIdx.y];
+  const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
+  float* out = eo.p[blockIdx.y];
+  if (!out) return;
+  const double* part = (const double*)(jb.ws + L.isum);
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kIsumParts; i += blockDim.x) v += part[i];
+  const double isum = block_sum(v, red);
+  const double* err = (const double*)(jb.ws + L.err);
+  for (int t = 0; t < jb.T; ++t) {
+    double e = 0.0;
+    for (int i = threadIdx.x; i < kErrSlots; i += blockDim.x) e += err[(size_t)t * kErrSlots + i];
+    e = block_sum(e, red);
+    if (threadIdx.x == 0) out[t] = (float)(isum > 0.0 ? e / isum : e);
+  }
 }
 
-static size_t rows_lds(int N, int M) { return (size_t)(N + M * N + N + 6 * M * N) * 8; }
-static size_t cols_lds(int N, int M) { return (size_t)(N + 2 * M * kCols * N) * 8; }
+// the final probe lives in buffer (J*T)&1; copy it back when that is the
+// workspace buffer
+__global__ void k_probe_back(const LaunchArgs a) {
+  const JobRec& jb = a.job[blockIdx.y];
+  if (((long long)jb.J * jb.T) % 2 == 0) return;
+  const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
+  const float2* src = (const float2*)(jb.ws + L.probe1);
+  const size_t n = (size_t)jb.M * jb.N * jb.N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    jb.probe[i] = src[i];
+}
 
-template <int N>
-static int sweep_impl(const mrpie_problem* pb, const mrpie_params* pr, SweepArgs& a, float* err_out,
-                      char* ws, const SweepLayout& L, hipStream_t s) {
-  const size_t lr = rows_lds(N, pb->M), lc = cols_lds(N, pb->M);
-  if (lr > 65536)
-    MRPIE_HIP(hipFuncSetAttribute((const void*)k_rows<N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr));
-  if (lc > 65536)
-    MRPIE_HIP(hipFuncSetAttribute((const void*)k_cols<N, kCols>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
-  const dim3 blk(256);
-  const int J = pb->J, T = pr->iterations;
-  auto rows = [&](int jn, int mode) {
-    TimingScope ts(TK_ROWS, s);
-    hipLaunchKernelGGL(k_rows<N>, dim3(N), blk, lr, s, a, jn, mode);
-  };
-  auto cols = [&](int jn) {
-    TimingScope ts(TK_COLS, s);
-    hipLaunchKernelGGL((k_cols<N, kCols>), dim3(N / kCols), blk, lc, s, a, jn);
-  };
-  for (int it = 0; it < T; ++it) {
-    for (int j = 0; j < J; ++j) {
-      rows(j, (it == 0 && j == 0) ? ROWS_HEAD : ROWS_MID);
-      cols(j);
+// ------------------------------------------------------------ tuning
+// Launch shapes of the sweep, per (N, batch class): FFT radix plan of each
+// pass and threads per row workgroup.  Defaults favour latency (radix 4,
+// 512 threads); mrpie_autotune measures the alternatives on the device.
+static Tuning g_tune[4][2];
+static bool g_tune_set[4][2];
+
+static int batch_class(int nb) { return nb > 1 ? 1 : 0; }
+
+Tuning get_tuning(int N, int M, int nb) {
+  (void)M;
+  const int ni = n_index(N), bc = batch_class(nb);
+  if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
+  return Tuning{4, 4, 512};
+}
+
+void set_tuning(int N, int nb, const Tuning& t) {
+  const int ni = n_index(N), bc = batch_class(nb);
+  if (ni < 0) return;
+  g_tune[ni][bc] = t;
+  g_tune_set[ni][bc] = true;
+}
+
+// ------------------------------------------------------------ host driver
+static size_t rows_lds(int N, int M) { return (size_t)(N + N + 6 * M * N) * 8; }
+static size_t cols_lds(int N, int M) { return (size_t)(N + 2 * M * N) * 8; }
+
+int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
+  int rc = launch_init_twiddles(s);
+  if (rc) return rc;
+  for (int c0 = 0; c0 < njobs; c0 += kMaxJobsPerLaunch) {
+    const int nb = std::min(kMaxJobsPerLaunch, njobs - c0);
+    LaunchArgs a{};
+    a.c = c;
+    a.njobs = nb;
+    int maxN = 64, maxTot = 0;
+    size_t lr = 0, lc = 0;
+    ErrOut eo{};
+    for (int b = 0; b < nb; ++b) {
+      a.job[b] = jobs[c0 + b];
+      const JobRec& jb = jobs[c0 + b];
+      maxN = std::max(maxN, jb.N);
+      maxTot = std::max(maxTot, jb.J * jb.T);
+      lr = std::max(lr, rows_lds(jb.N, jb.M));
+      lc = std::max(lc, cols_lds(jb.N, jb.M));
+      eo.p[b] = err_out ? err_out[c0 + b] : nullptr;
     }
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, (int*)(ws + L.iter));
+    const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+    const void* kr = tu.rows_radix == 8 ? (const void*)k_rows<false> : (const void*)k_rows<true>;
+    const void* kc = tu.cols_radix == 8 ? (const void*)k_cols<false> : (const void*)k_cols<true>;
+    if (lr > 65536) MRPIE_HIP(hipFuncSetAttribute(kr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr));
+    if (lc > 65536) MRPIE_HIP(hipFuncSetAttribute(kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+    const dim3 blk(256), rblk(tu.rows_threads);
+    hipLaunchKernelGGL(k_zero_err, dim3(8, nb), blk, 0, s, a);
+    if (maxTot == 0) continue;
+    for (int t = 0; t <= maxTot; ++t) {
+      {
+        TimingScope ts(TK_ROWS, s);
+        if (tu.rows_radix == 8) hipLaunchKernelGGL(k_rows<false>, dim3(maxN, nb), rblk, lr, s, a, t);
+        else hipLaunchKernelGGL(k_rows<true>, dim3(maxN, nb), rblk, lr, s, a, t);
+      }
+      if (t < maxTot) {
+        TimingScope ts(TK_COLS, s);
+        if (tu.cols_radix == 8) hipLaunchKernelGGL(k_cols<false>, dim3(maxN, nb), blk, lc, s, a, t);
+        else hipLaunchKernelGGL(k_cols<true>, dim3(maxN, nb), blk, lc, s, a, t);
+      }
+    }
+    hipLaunchKernelGGL(k_probe_back, dim3(64, nb), blk, 0, s, a);
+    hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), blk, 0, s, a);
+    hipLaunchKernelGGL(k_finish, dim3(1, nb), blk, 0, s, a, eo);
+    MRPIE_HIP(hipGetLastError());
   }
-  rows(0, ROWS_TAIL);
-  MRPIE_HIP(hipGetLastError());
-  // final probe lives in probe[(T*J)&1]
-  if (((long long)T * J) & 1) {
-    const size_t n = (size_t)pb->M * pb->N * pb->N;
-    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(256), 0, s, a.probe[0], (const float2*)a.probe[1], n);
-  }
-  if (err_out) {
-    const size_t nI = (size_t)J * pb->N * pb->N;
-    hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts), dim3(256), 0, s, a.I, nI, (double*)(ws + L.isum));
-    hipLaunchKernelGGL(k_finalize_err, dim3(1), dim3(256), 0, s, (const double*)(ws + L.err),
-                       (const double*)(ws + L.isum), kIsumParts, T, err_out);
-  }
-  MRPIE_HIP(hipGetLastError());
   return MRPIE_OK;
 }
 
@@ -406,6 +490,7 @@ int mrpie_validate(const mrpie_problem* pb, const mrpie_params* pr) {
   if (!(pr->beta >= 0.f && pr->beta <= 1.f)) return fail(MRPIE_EINVAL, "beta=%g not in [0,1]", pr->beta);
   if (!(pr->gamma >= 0.f && pr->gamma <= 1.f)) return fail(MRPIE_EINVAL, "gamma=%g not in [0,1]", pr->gamma);
   if (pr->iterations < 0 || pr->iterations > 100000) return fail(MRPIE_EINVAL, "iterations=%d", pr->iterations);
+  if ((long long)pr->iterations * pb->J >= (1LL << 30)) return fail(MRPIE_EINVAL, "iterations x J too large");
   if (pr->iter_offset < 0) return fail(MRPIE_EINVAL, "iter_offset=%d < 0", pr->iter_offset);
   if (pr->subpixel != 0 && pr->subpixel != 1) return fail(MRPIE_EINVAL, "subpixel must be 0 or 1");
   if (pr->refine != 0 && pr->refine != 1) return fail(MRPIE_EINVAL, "refine must be 0 or 1");
@@ -424,7 +509,7 @@ int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t
   int rc = mrpie_validate(pb, pr);
   if (rc) return rc;
   if (!bytes) return fail(MRPIE_EINVAL, "bytes is NULL");
-  *bytes = sweep_layout(pb, pr).total;
+  *bytes = ws_layout(pb->N, pb->M, pr->iterations).total;
   return MRPIE_OK;
 }
 
@@ -435,44 +520,57 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
   if (rc) return rc;
   if (!obj || !probe || !pos || !intens) return fail(MRPIE_EINVAL, "null array pointer");
   if (pr->refine && !adam) return fail(MRPIE_EINVAL, "adam state is NULL with refine = 1");
-  const SweepLayout L = sweep_layout(pb, pr);
+  const WsLayout L = ws_layout(pb->N, pb->M, pr->iterations);
   if (!ws || ws_bytes < L.total) return fail(MRPIE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
   if (pr->iterations == 0) return MRPIE_OK;
-  hipStream_t s = (hipStream_t)stream;
-  char* w = (char*)ws;
-  SweepArgs a{};
-  a.H = pb->H; a.W = pb->W; a.N = pb->N; a.M = pb->M; a.J = pb->J; a.T = pr->iterations;
-  a.alpha_obj = pr->alpha_obj; a.alpha_probe = pr->alpha_probe; a.beta = pr->beta; a.gamma = pr->gamma;
-  a.iter_offset = pr->iter_offset; a.probe_update_start = pr->probe_update_start;
-  a.obj = (float2*)obj;
-  a.probe[0] = (float2*)probe;
-  a.probe[1] = (float2*)(w + L.probe1);
-  a.pos = pos;
-  a.I = intens;
-  for (int i = 0; i < 2; ++i) {
-    a.psi[i] = (float2*)(w + L.psi[i]);
-    a.patch[i] = (float2*)(w + L.patch[i]);
-    a.pmax[i] = (float*)(w + L.pmax[i]);
-    a.omax[i] = (float*)(w + L.omax[i]);
-    a.box[i] = (int*)(w + L.box[i]);
+  Common c{pr->alpha_obj, pr->alpha_probe, pr->beta, pr->gamma, pr->iter_offset, pr->probe_update_start};
+  JobRec jb{(float2*)obj, (float2*)probe, pos, intens, (char*)ws, status,
+            pb->H, pb->W, pb->N, pb->M, pb->J, pr->iterations};
+  float* eo[1] = {err_out};
+  return run_sweep(c, &jb, 1, eo, (hipStream_t)stream);
+}
+
+int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
+  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", N);
+  if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
+  if ((t->rows_radix != 4 && t->rows_radix != 8) || (t->cols_radix != 4 && t->cols_radix != 8))
+    return fail(MRPIE_EINVAL, "radix must be 4 or 8");
+  if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
+  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads});
+  return MRPIE_OK;
+}
+
+int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
+  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", N);
+  if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
+  const Tuning u = get_tuning(N, 1, batched ? 2 : 1);
+  t->rows_radix = u.rows_radix;
+  t->cols_radix = u.cols_radix;
+  t->rows_threads = u.rows_threads;
+  return MRPIE_OK;
+}
+
+int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream) {
+  if (njobs < 0) return fail(MRPIE_EINVAL, "njobs=%d < 0", njobs);
+  if (njobs == 0) return MRPIE_OK;
+  if (!jobs || !pr) return fail(MRPIE_EINVAL, "null jobs or params");
+  std::vector<JobRec> recs((size_t)njobs);
+  std::vector<float*> errs((size_t)njobs);
+  for (int b = 0; b < njobs; ++b) {
+    const mrpie_job& j = jobs[b];
+    int rc = mrpie_validate(&j.problem, pr);
+    if (rc) return fail(rc, "job %d: %s", b, mrpie_last_error());
+    if (!j.obj || !j.probe || !j.pos || !j.intens) return fail(MRPIE_EINVAL, "job %d: null array pointer", b);
+    const WsLayout L = ws_layout(j.problem.N, j.problem.M, pr->iterations);
+    if (!j.ws || j.ws_bytes < L.total)
+      return fail(MRPIE_EWORKSPACE, "job %d: workspace %zu < %zu bytes", b, j.ws_bytes, L.total);
+    recs[b] = JobRec{(float2*)j.obj, (float2*)j.probe, j.pos, j.intens, (char*)j.ws, j.status,
+                     j.problem.H, j.problem.W, j.problem.N, j.problem.M, j.problem.J, pr->iterations};
+    errs[b] = j.err_out;
   }
-  a.err_acc = (double*)(w + L.err);
-  a.status = status;
-  a.iter_dev = (const int*)(w + L.iter);
-  rc = launch_init_twiddles(s);
-  if (rc) return rc;
-  // clear the error accumulators and the iteration counter (fill kernel:
-  // safe under graph capture)
-  hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, s, (int*)(w + L.err),
-                     (size_t)pr->iterations * kErrSlots * 2);
-  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (int*)(w + L.iter), (size_t)4);
-  MRPIE_HIP(hipGetLastError());
-  switch (pb->N) {
-    case 64: return sweep_impl<64>(pb, pr, a, err_out, w, L, s);
-    case 128: return sweep_impl<128>(pb, pr, a, err_out, w, L, s);
-    case 192: return sweep_impl<192>(pb, pr, a, err_out, w, L, s);
-    default: return sweep_impl<256>(pb, pr, a, err_out, w, L, s);
-  }
+  if (pr->iterations == 0) return MRPIE_OK;
+  Common c{pr->alpha_obj, pr->alpha_probe, pr->beta, pr->gamma, pr->iter_offset, pr->probe_update_start};
+  return run_sweep(c, recs.data(), njobs, errs.data(), (hipStream_t)stream);
 }
 
 }  // extern "C"

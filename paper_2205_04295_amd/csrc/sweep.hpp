@@ -1,0 +1,82 @@
+// Data structures of the M-rPIE sweep shared by the plain and batched
+// drivers (Methods, "M-rPIE algorithm", Eq. 4-7).
+#pragma once
+#include "common.hpp"
+
+namespace mrpie {
+
+constexpr int kErrSlots = 256;   // per-iteration error partials (one per column unit)
+constexpr int kIsumParts = 256;  // partial sums of the intensities
+constexpr int kMaxJobsPerLaunch = 36;
+
+// Parameters shared by all jobs of one call.
+struct Common {
+  float alpha_obj, alpha_probe, beta, gamma;
+  int iter_offset, probe_update_start;
+};
+
+// One reconstruction (job).  `ws` is this job's private workspace.
+struct JobRec {
+  float2* obj;        // [H][W]
+  float2* probe;      // [M][N][N]  (probe buffer 0: the caller's array)
+  const float* pos;   // [J][2]
+  const float* I;     // [J][N][N]
+  char* ws;
+  int* status;
+  int H, W, N, M, J, T;
+};
+
+struct LaunchArgs {
+  Common c;
+  int njobs;
+  JobRec job[kMaxJobsPerLaunch];
+};
+
+// Workspace layout of one job; identical on host and device.
+struct WsLayout {
+  size_t psi[2], patch[2], probe1, pmax[2], omax[2], box[2], err, isum, total;
+};
+
+__host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ __device__ inline WsLayout ws_layout(int N, int M, int T) {
+  WsLayout L{};
+  const size_t NN = (size_t)N * N;
+  size_t off = 0;
+#define MRPIE_TAKE(field, bytes) \
+  field = off;                   \
+  off = ws_align(off + (bytes));
+  MRPIE_TAKE(L.psi[0], M * NN * 8)
+  MRPIE_TAKE(L.psi[1], M * NN * 8)
+  MRPIE_TAKE(L.patch[0], NN * 8)
+  MRPIE_TAKE(L.patch[1], NN * 8)
+  MRPIE_TAKE(L.probe1, M * NN * 8)
+  MRPIE_TAKE(L.pmax[0], (size_t)N * 4)
+  MRPIE_TAKE(L.pmax[1], (size_t)N * 4)
+  MRPIE_TAKE(L.omax[0], (size_t)N * 4)
+  MRPIE_TAKE(L.omax[1], (size_t)N * 4)
+  MRPIE_TAKE(L.box[0], 16)
+  MRPIE_TAKE(L.box[1], 16)
+  MRPIE_TAKE(L.err, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)
+  MRPIE_TAKE(L.isum, (size_t)kIsumParts * 8)
+#undef MRPIE_TAKE
+  L.total = off;
+  return L;
+}
+
+// Launch shape of the two sweep passes (chosen per N and batch class).
+struct Tuning {
+  int rows_radix;    // 4 or 8: FFT plan of the row pass
+  int cols_radix;    // 4 or 8: FFT plan of the column pass
+  int rows_threads;  // 256 or 512 threads per row workgroup
+};
+Tuning get_tuning(int N, int M, int nb);
+void set_tuning(int N, int nb, const Tuning& t);
+
+// Host driver: runs `T` iterations (per job) of the sweep for every job in
+// `jobs` (any mix of N and M), lock-step by position: tick t performs the
+// transition (t-1 -> t) row pass and the column pass of step t of every job
+// that has one.  Writes err_out[b][T_b] when err_out[b] != nullptr.
+int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s);
+
+}  // namespace mrpie

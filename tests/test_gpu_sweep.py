@@ -175,3 +175,29 @@ def test_out_of_range_position_is_clamped_and_flagged():
                      np.clip(w.pos0, 0, 128).astype(np.float32), w.params)
     o = run_oracle(wc, prm)
     assert rel_l2(g["O"], o["O"]) < 1e-4
+
+
+@pytest.mark.parametrize("name", ["n128m2", "n192m5"])
+def test_every_launch_shape_matches_oracle(name):
+    """Each candidate of the autotuner (FFT radix per pass, row threads)
+    computes the same sweep to the parity tolerance."""
+    from paper_2205_04295_amd import tune
+    w = wl.small_case(name=name, **CASES[name])
+    prm = dict(w.params, iterations=1)
+    o = run_oracle(w, prm)
+    N = w.P0.shape[-1]
+    saved = tune.get_tuning(N, False)
+    try:
+        for cand in tune.CANDIDATES:
+            tune.set_tuning(N, False, **cand)
+            g = run_gpu(w, prm)
+            assert rel_l2(g["O"], o["O"]) < 1e-4 and rel_l2(g["P"], o["P"]) < 1e-4, cand
+    finally:
+        tune.set_tuning(N, False, **saved)
+
+
+def test_autotuner_installs_a_candidate():
+    from paper_2205_04295_amd import tune
+    best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
+    assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
+    assert tune.get_tuning(64, False) == best
