@@ -37,6 +37,12 @@ def parse():
                     help="positions in the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--batch", type=int, default=8,
                     help="independent 256^2 x 3 reconstructions in the batched measurement (0 = skip)")
+    ap.add_argument("--refine-iters", type=int, default=10,
+                    help="iterations of the position-refinement workload (0 = skip)")
+    ap.add_argument("--adjoint", type=int, default=1, help="measure loss + gradient (0 = skip)")
+    ap.add_argument("--uneven", type=float, default=0.25,
+                    help="scan-length scale of the 64-job uneven batch (0 = skip, 1 = full)")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep launch shapes first")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -101,6 +107,100 @@ def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_
             "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()}}
 
 
+def measure_refine(api, torch, dev, args):
+    """Position refinement on the sigma = 3 px error workload: subpixel sweep
+    + XCORR_A registration + Adam every iteration; reports positions x
+    iterations / s and the position RMS error vs the truth before / after."""
+    import numpy as np
+    from synth import workloads as wl
+    t0 = time.time()
+    w = wl.refine_case(seed=2)
+    gen = time.time() - t0
+    J = w.pos0.shape[0]
+    obj = torch.from_numpy(w.O0).to(dev)
+    probe = torch.from_numpy(w.P0).to(dev)
+    pos = torch.from_numpy(w.pos0).to(dev)
+    I = torch.from_numpy(w.I).to(dev)
+    adam = torch.zeros(J, 4, dtype=torch.float32, device=dev)
+    prm = dict(w.params)
+    prm.pop("iterations", None)
+    T = args.refine_iters
+
+    def rms(p):
+        d = p - w.pos_true.astype(np.float64)
+        return float(np.sqrt(np.mean(np.sum(d * d, axis=1)))), \
+            float(np.sqrt(np.mean(np.sum((d - d.mean(0)) ** 2, axis=1))))
+    before = rms(w.pos0.astype(np.float64))
+    ws = None
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for it in range(T):
+        ws = api.rpie(obj, probe, pos, I, adam=adam, workspace=ws, iterations=1, iter_offset=it, **prm)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    after = rms(pos.cpu().numpy().astype(np.float64))
+    return {"workload": "spiral256x3 with N(0, 3 px) position errors, subpixel Fourier moves, XCORR_A "
+                        "registration (upsample 100, phase correlation) + Adam (lr 0.5) every iteration",
+            "iterations": T, "value": round(J * T / el, 1), "unit": "positions*iter/s",
+            "ms_per_iter": round(el * 1e3 / T, 3),
+            "pos_rms_px_before": [round(x, 4) for x in before], "pos_rms_px_after": [round(x, 4) for x in after],
+            "rms_note": "[raw, mean-offset removed]", "datagen_s": round(gen, 1)}
+
+
+def measure_adjoint(api, torch, dev, obj, probe, pos, I, args):
+    """Loss + gradient (object, probe, positions) over all 1600 positions of
+    the spiral workload, float32; positions / s of one evaluation."""
+    for _ in range(2):
+        api.adjoint(obj, probe, pos, I, subpixel=1)
+    torch.cuda.synchronize()
+    n = 3
+    t0 = time.perf_counter()
+    for _ in range(n):
+        L, gO, gP, gp = api.adjoint(obj, probe, pos, I, subpixel=1)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / n
+    J = pos.shape[0]
+    return {"value": round(J / el, 1), "unit": "positions/s (loss + gradient)", "ms_per_eval": round(el * 1e3, 3),
+            "loss": float(L.item())}
+
+
+def measure_uneven(api, torch, dev, args):
+    """64 independent reconstructions of uneven N, M, J run in shared
+    launches vs the same jobs run one after another through the plain sweep."""
+    from synth import workloads as wl
+    t0 = time.time()
+    jobs_np = wl.batch_jobs(seed=4, jscale=args.uneven, iterations=20)
+    gen = time.time() - t0
+    T = 2
+
+    def mk():
+        return [dict(obj=torch.from_numpy(j.O0).to(dev), probe=torch.from_numpy(j.P0).to(dev),
+                     pos=torch.from_numpy(j.pos0).to(dev), intens=torch.from_numpy(j.I).to(dev)) for j in jobs_np]
+    prm = dict(jobs_np[0].params)
+    prm.pop("iterations", None)
+    total = sum(j.pos0.shape[0] for j in jobs_np) * T
+    jobs = mk()
+    api.rpie_batched(jobs, iterations=1, **prm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.rpie_batched(jobs, iterations=T, **prm)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t1
+    jobs = mk()
+    for j in jobs:
+        api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], iterations=1, **prm)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for j in jobs:
+        api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], iterations=T, **prm)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t2
+    return {"jobs": len(jobs_np), "scan_scale": args.uneven, "iterations": T,
+            "batched_value": round(total / el_b, 1), "sequential_value": round(total / el_s, 1),
+            "unit": "positions*iter/s (aggregate)", "speedup": round(el_s / el_b, 2),
+            "N_mix": sorted({int(j.P0.shape[-1]) for j in jobs_np}), "datagen_s": round(gen, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -127,6 +227,11 @@ def main():
     prm = dict(w.params)
     prm.pop("iterations", None)
 
+    tuned = None
+    if args.autotune:
+        from paper_2205_04295_amd import tune
+        tuned = {"plain": tune.autotune(N, M, batch=1, J=128, reps=2)[0],
+                 "batched": tune.autotune(N, M, batch=max(2, args.batch), J=64, reps=1)[0]}
     ws = None
     for it in range(args.warmup):
         ws = api.rpie(obj, probe, pos, I, err=err, status=status, workspace=ws, iterations=1,
@@ -158,6 +263,10 @@ def main():
     batched = None
     if args.batch > 0:
         batched = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b)
+
+    refine = measure_refine(api, torch, dev, args) if args.refine_iters > 0 else None
+    adjoint = measure_adjoint(api, torch, dev, obj, probe, pos, I, args) if args.adjoint else None
+    uneven = measure_uneven(api, torch, dev, args) if args.uneven > 0 else None
 
     if args.calib:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -197,6 +306,10 @@ def main():
         "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
         "path_algorithmic_GBs": round(path_gbs, 1),
         "batched": batched,
+        "refine": refine,
+        "adjoint": adjoint,
+        "uneven_batch": uneven,
+        "tuning": tuned,
         "cpu_baseline": cpu,
         "status": int(status.item()),
         "final_error": float(err.item()),

@@ -176,6 +176,53 @@ int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream);
  * is 0. */
 int mrpie_modulus(int32_t N, int32_t M, void* psi, const float* intens, void* stream);
 
+/* Subpixel registration of B pairs of N x N complex64 patches (Methods,
+ * "Adam-based position refinement": 2-D phase correlation after
+ * Guizar-Sicairos et al. 2008 with the matrix-multiply DFT evaluated only
+ * around the coarse peak, no zero-padding).
+ *  ref, mov [B][N][N] complex64 device arrays (pairs b = ref[b], mov[b])
+ *  upsample : up >= 1; window U = ceil(1.5 up) samples per axis at spacing
+ *             1/up, centred (index floor(U/2)) on the integer peak
+ *  norm     : 0 = plain cross-power F(ref) conj(F(mov)); 1 = divided by its
+ *             modulus (zero where the modulus is zero)
+ *  shift [B][2] float32 out: (y, x) with mov(r) ~ ref(r + shift)
+ *  peak  [B][4] int32 out: coarse argmax (row, col) of |F^-1 X| in FFT
+ *             order (lags above N/2 are negative) and window argmax (u, v);
+ *             ties go to the first maximum in row-major order
+ * Computed in double precision throughout.  Workspace:
+ * mrpie_register_workspace_size(N, B, upsample). */
+int mrpie_register_workspace_size(int32_t N, int32_t B, int32_t upsample, size_t* bytes);
+int mrpie_register(int32_t N, int32_t B, const void* ref, const void* mov, int32_t upsample, int32_t norm,
+                   float* shift, int32_t* peak, void* ws, size_t ws_bytes, void* stream);
+
+/* Modified Adam step of Alg. 1 for J positions (one reconstruction
+ * iteration t >= 1): g [J][2] is the measured shift (the gradient);
+ * adam [J][4] = (m_y, m_x, v_y, v_x) in/out; pos [J][2] in/out moves by
+ * +adam_lr * mhat / (sqrt(vhat) + adam_eps) per axis (Eq. 8-9) and is
+ * clamped to [0, ymax] x [0, xmax] (ymax = H - N, xmax = W - N). */
+int mrpie_adam(int32_t J, const mrpie_params* pr, int32_t ymax, int32_t xmax, float* pos, float* adam,
+               const float* g, int32_t t, void* stream);
+
+/* Amplitude loss of the mixed-state forward model (Eq. 4, with the crop of
+ * box j moved by the fractional position when subpixel = 1) and its
+ * hand-written adjoint.
+ *   L = sum_j sum_k (A_j(k) - sqrt(max(I_j(k), 0)))^2,
+ *   A_j = sqrt(sum_p |D_z(P_p o_j)|^2),  o_j = S_f(crop of obj at pos[j])
+ * mrpie_loss writes L (double, device) to loss_out.  mrpie_adjoint also
+ * writes (overwriting) the gradients of L w.r.t. the object grad_obj [H][W]
+ * and the probe modes grad_probe [M][N][N] (complex64, dL/dRe + i dL/dIm),
+ * and w.r.t. the positions grad_pos [J][2] float32 through the Fourier
+ * shift (zero when subpixel = 0; the integer corner is piecewise constant).
+ * loss_out may be NULL for mrpie_adjoint.  Exit waves are recomputed, not
+ * stored; overlapping boxes and the probe sum are reduced in position order
+ * (deterministic).  Workspace: mrpie_grad_workspace_size. */
+int mrpie_grad_workspace_size(const mrpie_problem* pb, size_t* bytes);
+int mrpie_loss(const mrpie_problem* pb, int32_t subpixel, const void* obj, const void* probe, const float* pos,
+               const float* intens, double* loss_out, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+int mrpie_adjoint(const mrpie_problem* pb, int32_t subpixel, const void* obj, const void* probe, const float* pos,
+                  const float* intens, double* loss_out, void* grad_obj, void* grad_probe, float* grad_pos,
+                  int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Diagnostic kernel timing (not for use under graph capture).
  * mrpie_timing_enable(stride): from now on, every stride-th launch of each
  * timed kernel class is bracketed by a HIP event pair on the stream it is

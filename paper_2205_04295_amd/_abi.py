@@ -74,6 +74,13 @@ _SIGS = {
     "mrpie_rpie_batched": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Params), _P]),
     "mrpie_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "mrpie_get_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "mrpie_register_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "mrpie_register": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
+    "mrpie_adam": (C.c_int, [C.c_int32, C.POINTER(Params), C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
+    "mrpie_grad_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(C.c_size_t)]),
+    "mrpie_loss": (C.c_int, [C.POINTER(Problem), C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "mrpie_adjoint": (C.c_int, [C.POINTER(Problem), C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                C.c_size_t, _P]),
     "mrpie_fft2": (C.c_int, [C.c_int32, C.c_int32, _P, C.c_int32, _P]),
     "mrpie_modulus": (C.c_int, [C.c_int32, C.c_int32, _P, _P, _P]),
     "mrpie_timing_enable": (C.c_int, [C.c_int32]),

@@ -96,6 +96,99 @@ def rpie_batched(jobs, stream=None, **params):
     return keep
 
 
+def register(ref, mov, upsample=100, norm=1, workspace=None, stream=None):
+    """Subpixel registration of pairs ref[b], mov[b] ([B, N, N] complex64).
+    Returns (shift [B, 2] float32, peak [B, 4] int32) on the GPU."""
+    lib = _abi.load()
+    B, N, _ = ref.shape
+    if mov.shape != ref.shape:
+        raise ValueError("ref and mov shapes differ")
+    n = C.c_size_t(0)
+    check(lib.mrpie_register_workspace_size(N, B, upsample, C.byref(n)))
+    if workspace is None or workspace.numel() < n.value:
+        workspace = torch.empty(n.value, dtype=torch.uint8, device=ref.device)
+    shift = torch.empty(B, 2, dtype=torch.float32, device=ref.device)
+    peak = torch.empty(B, 4, dtype=torch.int32, device=ref.device)
+    check(lib.mrpie_register(N, B, _dev(ref, torch.complex64, "ref"), _dev(mov, torch.complex64, "mov"),
+                             upsample, norm, _dev(shift, torch.float32, "shift"), _dev(peak, torch.int32, "peak"),
+                             _dev(workspace, torch.uint8, "workspace"), C.c_size_t(workspace.numel()),
+                             _stream(stream)))
+    return shift, peak
+
+
+def adam(pos, state, g, t, bounds, stream=None, **params):
+    """Alg. 1 step in place on pos [J, 2] and state [J, 4] with gradient g [J, 2]."""
+    lib = _abi.load()
+    prm = make_params(**params)
+    check(lib.mrpie_adam(pos.shape[0], C.byref(prm), int(bounds[0]), int(bounds[1]),
+                         _dev(pos, torch.float32, "pos"), _dev(state, torch.float32, "state"),
+                         _dev(g, torch.float32, "g"), int(t), _stream(stream)))
+    return pos, state
+
+
+def _grad_ws(pb, device, workspace):
+    lib = _abi.load()
+    n = C.c_size_t(0)
+    check(lib.mrpie_grad_workspace_size(C.byref(pb), C.byref(n)))
+    if workspace is None or workspace.numel() < n.value:
+        workspace = torch.empty(n.value, dtype=torch.uint8, device=device)
+    return workspace
+
+
+def loss(obj, probe, pos, intens, subpixel=1, workspace=None, stream=None):
+    """Amplitude loss (float64 GPU scalar tensor) of the forward model."""
+    lib = _abi.load()
+    pb = problem_of(obj, probe, pos)
+    ws = _grad_ws(pb, obj.device, workspace)
+    out = torch.empty((), dtype=torch.float64, device=obj.device)
+    check(lib.mrpie_loss(C.byref(pb), int(subpixel), _dev(obj, torch.complex64, "obj"),
+                         _dev(probe, torch.complex64, "probe"), _dev(pos, torch.float32, "pos"),
+                         _dev(intens, torch.float32, "intens"), C.c_void_p(out.data_ptr()), C.c_void_p(None),
+                         _dev(ws, torch.uint8, "workspace"), C.c_size_t(ws.numel()), _stream(stream)))
+    return out
+
+
+def adjoint(obj, probe, pos, intens, subpixel=1, workspace=None, stream=None):
+    """(loss, grad_obj, grad_probe, grad_pos) of the amplitude loss."""
+    lib = _abi.load()
+    pb = problem_of(obj, probe, pos)
+    ws = _grad_ws(pb, obj.device, workspace)
+    out = torch.empty((), dtype=torch.float64, device=obj.device)
+    gO = torch.empty_like(obj)
+    gP = torch.empty_like(probe)
+    gp = torch.empty_like(pos)
+    check(lib.mrpie_adjoint(C.byref(pb), int(subpixel), _dev(obj, torch.complex64, "obj"),
+                            _dev(probe, torch.complex64, "probe"), _dev(pos, torch.float32, "pos"),
+                            _dev(intens, torch.float32, "intens"), C.c_void_p(out.data_ptr()),
+                            _dev(gO, torch.complex64, "grad_obj"), _dev(gP, torch.complex64, "grad_probe"),
+                            _dev(gp, torch.float32, "grad_pos"), C.c_void_p(None),
+                            _dev(ws, torch.uint8, "workspace"), C.c_size_t(ws.numel()), _stream(stream)))
+    return out, gO, gP, gp
+
+
+class ForwardModel(torch.autograd.Function):
+    """Amplitude loss of the mixed-state far-field model as an autograd
+    Function: forward runs the HIP loss passes, backward the HIP adjoint
+    (which recomputes the exit waves instead of saving them).
+
+    ForwardModel.apply(obj, probe, pos, intens[, subpixel]) -> scalar loss.
+    """
+
+    @staticmethod
+    def forward(ctx, obj, probe, pos, intens, subpixel=1):
+        obj_c, probe_c, pos_c = obj.detach().contiguous(), probe.detach().contiguous(), pos.detach().contiguous()
+        ctx.save_for_backward(obj_c, probe_c, pos_c, intens)
+        ctx.subpixel = subpixel
+        return loss(obj_c, probe_c, pos_c, intens, subpixel).to(torch.float32)
+
+    @staticmethod
+    def backward(ctx, g):
+        obj, probe, pos, intens = ctx.saved_tensors
+        _, gO, gP, gp = adjoint(obj, probe, pos, intens, ctx.subpixel)
+        g = g.to(torch.float32)
+        return gO * g, gP * g, gp * g, None, None
+
+
 def fft2(x, inverse=False, stream=None):
     """In-place unitary 2-D DFT of x [..., N, N] complex64 (test hook)."""
     lib = _abi.load()
@@ -121,7 +214,7 @@ def validate(problem: Problem, **params) -> int:
     return lib.mrpie_validate(C.byref(problem), C.byref(prm))
 
 
-TIMED_KERNELS = ("k_rows", "k_cols")
+TIMED_KERNELS = ("k_rows", "k_cols", "reg_fft", "reg_gemm", "adj_fwd")
 
 
 def timing_enable(stride: int):

@@ -1,0 +1,537 @@
+// Amplitude loss of the mixed-state forward model and its hand-written
+// adjoint (gradients w.r.t. object, probe modes and subpixel positions) on
+// gfx950.  The forward model is the paper's Eq. 4 with the crop moved by a
+// band-limited Fourier shift; the loss and adjoint are an extension of it:
+//
+//   o_j = S_f(crop_j),  Psi_pj = F(P_p o_j),  A_j = sqrt(sum_p |Psi_pj|^2)
+//   L   = sum_j sum_k (A_j - sqrt(I_j))^2
+//   chi_pj = F^-1((1 - sqrt(I_j)/A_j) Psi_pj)            (0 where A_j = 0)
+//   dL/dP_p   = 2 sum_j conj(o_j) chi_pj
+//   dL/do_j   = g_j = 2 sum_p conj(P_p) chi_pj
+//   dL/dO     = sum_j S_{-f}(g_j) scattered into box j
+//   dL/df_j   = Re sum_k conj(F g_j)(k) (2 pi i k / N) (F o_j)(k)
+// (gradients of complex arrays in the dL/dRe + i dL/dIm convention; F is the
+// unitary DFT.)  Nothing is stored between the forward and backward passes:
+// the backward recomputes the exit waves.
+//
+// Positions are independent, so every pass runs on a chunk of positions at
+// once (grid.y = position in chunk), with the 2-D FFTs split into row and
+// column passes like the sweep.  Overlapping boxes and the probe sum are
+// reduced in position order by separate kernels, never with atomics, so the
+// result is deterministic.
+#include <algorithm>
+#include <cmath>
+
+#include "adjoint.hpp"
+
+namespace mrpie {
+
+__device__ __forceinline__ size_t chunk_off(int b, int N) { return (size_t)b * N * N; }
+
+// P1 (rows): gather crop row r of position j0 + b, row FFT -> Cp
+template <int N>
+__device__ void adj_p1(const AdjArgs& a, float2* smem) {
+  const int r = blockIdx.x, b = blockIdx.y;
+  const int j = a.j0 + b;
+  float2* tw = smem;
+  float2* A = tw + N;
+  float2* B = A + N;
+  const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
+  const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
+  const int c = threadIdx.x;
+  float2 v = make_float2(0.f, 0.f);
+  if (c < N) v = a.obj[(size_t)(ny + r) * a.W + nx + c];
+  load_twiddles<N>(tw);
+  if (c < N) A[c] = v;
+  __syncthreads();
+  float2* R = fft_lds<N, false>(A, B, 1, tw);
+  if (c < N) a.Cp[chunk_off(b, N) + (size_t)r * N + c] = R[c];
+}
+
+__device__ __forceinline__ void frac_of(const AdjArgs& a, int j, int N, float* fy, float* fx) {
+  *fy = 0.f;
+  *fx = 0.f;
+  if (!a.subpixel) return;
+  const float py = a.pos[2 * j], px = a.pos[2 * j + 1];
+  const float qy = floorf(py + 0.5f), qx = floorf(px + 0.5f);
+  if (qy >= 0.f && qy <= (float)(a.H - N)) *fy = py - qy;
+  if (qx >= 0.f && qx <= (float)(a.W - N)) *fx = px - qx;
+}
+
+__device__ __forceinline__ float2 ramp(int ky, int kx, float fy, float fx, float sg, int N) {
+  float sn, cs;
+  sincospif(sg * 2.f * ((float)ky * fy + (float)kx * fx) / (float)N, &sn, &cs);
+  return make_float2(cs, sn);
+}
+
+// P2 (cols): F(crop) -> F(o) = F(crop) e^{+2 pi i k.f/N}; stores F(o)
+// (unnormalised) and the inverse column pass of F(o)/N^2 into Cp
+template <int N>
+__device__ void adj_p2(const AdjArgs& a, float2* smem) {
+  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y;
+  if (u >= N) return;
+  const int j = a.j0 + b;
+  float fy, fx;
+  frac_of(a, j, N, &fy, &fx);
+  float2* tw = smem;
+  float2* A = tw + N;
+  float2* B = A + N;
+  const int k = threadIdx.x;
+  float2* cp = a.Cp + chunk_off(b, N);
+  float2 v = make_float2(0.f, 0.f);
+  if (k < N) v = cp[(size_t)k * N + u];
+  load_twiddles<N>(tw);
+  if (k < N) A[k] = v;
+  __syncthreads();
+  float2* F = fft_lds<N, false>(A, B, 1, tw);
+  float2* G = (F == A) ? B : A;
+  if (k < N) {
+    const int ky = k < N / 2 ? k : k - N, kx = u < N / 2 ? u : u - N;
+    const float2 fo = cmul(F[k], ramp(ky, kx, fy, fx, 1.f, N));
+    a.Fo[chunk_off(b, N) + (size_t)k * N + u] = fo;
+    G[k] = cscale(fo, 1.f / ((float)N * (float)N));
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true>(G, F, 1, tw);
+  if (k < N) cp[(size_t)k * N + u] = H[k];
+}
+
+// P3 (rows): o row r; exit waves P_p o, row FFTs -> Psi
+template <int N>
+__device__ void adj_p3(const AdjArgs& a, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const int r = blockIdx.x, b = blockIdx.y, M = a.M;
+  const size_t NN = (size_t)N * N;
+  float2* tw = smem;
+  float2* A = tw + N;            // (M+1) N
+  float2* B = A + (M + 1) * N;   // (M+1) N
+  const int c = threadIdx.x;
+  float2* cp = a.Cp + chunk_off(b, N);
+  float2 v = make_float2(0.f, 0.f), P[MM];
+  if (c < N) {
+    v = cp[(size_t)r * N + c];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) P[p] = a.probe[p * NN + (size_t)r * N + c];
+  }
+  load_twiddles<N>(tw);
+  if (c < N) A[c] = v;
+  __syncthreads();
+  float2* R = fft_lds<N, true>(A, B, 1, tw);
+  float2* W = (R == A) ? B : A;
+  if (c < N) {
+    const float2 o = R[c];
+    cp[(size_t)r * N + c] = o;  // Cp now holds o
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) W[p * N + c] = cmul(P[p], o);
+  }
+  __syncthreads();
+  float2* S = fft_lds<N, false>(W, R, M, tw);
+  float2* psi = a.Psi + (size_t)b * M * NN;
+  for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
+    const int p = i / N, cc = i - p * N;
+    psi[p * NN + (size_t)r * N + cc] = S[i];
+  }
+}
+
+// P4 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
+template <int N>
+__device__ void adj_p4(const AdjArgs& a, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y, M = a.M;
+  if (u >= N) return;
+  const int j = a.j0 + b;
+  const size_t NN = (size_t)N * N;
+  float2* tw = smem;
+  float2* A = tw + N;        // M N
+  float2* B = A + M * N;     // M N
+  __shared__ double redd[16];
+  const int k = threadIdx.x;
+  float2* psi = a.Psi + (size_t)b * M * NN;
+  float2 v[MM];
+  float Iv = 0.f;
+  if (k < N) {
+    Iv = a.I[(size_t)j * NN + (size_t)k * N + u];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) v[p] = psi[p * NN + (size_t)k * N + u];
+  }
+  load_twiddles<N>(tw);
+  if (k < N) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) A[p * N + k] = v[p];
+  }
+  __syncthreads();
+  float2* F = fft_lds<N, false>(A, B, M, tw);
+  float2* G = (F == A) ? B : A;
+  double e = 0.0;
+  if (k < N) {
+    const float invN = 1.f / (float)N;
+    float S = 0.f;
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) S += cabs2(F[p * N + k]);
+    const float Au = sqrtf(S);
+    const float sq = sqrtf(fmaxf(Iv, 0.f));
+    const float d = Au * invN - sq;
+    e = (double)d * (double)d;
+    // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
+    // inverse 2-D transform
+    const float wgt = Au > 0.f ? (1.f - sq * (float)N / Au) * invN * invN : 0.f;
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) G[p * N + k] = cscale(F[p * N + k], wgt);
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true>(G, F, M, tw);
+  if (k < N) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) psi[p * NN + (size_t)k * N + u] = H[p * N + k];
+  }
+  e = block_sum(e, redd);
+  if (threadIdx.x == 0) a.loss_part[(size_t)b * N + u] = e;
+}
+
+// P5 (rows): chi row r; probe-gradient terms 2 conj(o) chi_p (kept per
+// position for the ordered reduction); g = 2 sum_p conj(P_p) chi_p, row FFT
+template <int N>
+__device__ void adj_p5(const AdjArgs& a, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const int r = blockIdx.x, b = blockIdx.y, M = a.M;
+  const size_t NN = (size_t)N * N;
+  float2* tw = smem;
+  float2* A = tw + N;       // M N
+  float2* B = A + M * N;    // M N
+  const int c = threadIdx.x;
+  float2* psi = a.Psi + (size_t)b * M * NN;
+  float2 v[MM], P[MM];
+  float2 o = make_float2(0.f, 0.f);
+  if (c < N) {
+    o = a.Cp[chunk_off(b, N) + (size_t)r * N + c];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        v[p] = psi[p * NN + (size_t)r * N + c];
+        P[p] = a.probe[p * NN + (size_t)r * N + c];
+      }
+  }
+  load_twiddles<N>(tw);
+  if (c < N) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) A[p * N + c] = v[p];
+  }
+  __syncthreads();
+  float2* R = fft_lds<N, true>(A, B, M, tw);
+  float2* W = (R == A) ? B : A;
+  if (c < N) {
+    float2 g = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        const float2 chi = R[p * N + c];
+        psi[p * NN + (size_t)r * N + c] = cscale(cmulc(chi, o), 2.f);   // 2 chi conj(o)
+        g = cadd(g, cmulc(chi, P[p]));
+      }
+    W[c] = cscale(g, 2.f);
+  }
+  __syncthreads();
+  float2* S = fft_lds<N, false>(W, R, 1, tw);
+  if (c < N) a.G[chunk_off(b, N) + (size_t)r * N + c] = S[c];
+}
+
+// P6 (cols): F(g); position-gradient partials; S_{-f}: x e^{-2 pi i k.f/N}/N^2
+template <int N>
+__device__ void adj_p6(const AdjArgs& a, float2* smem) {
+  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y;
+  if (u >= N) return;
+  const int j = a.j0 + b;
+  float fy, fx;
+  frac_of(a, j, N, &fy, &fx);
+  float2* tw = smem;
+  float2* A = tw + N;
+  float2* B = A + N;
+  __shared__ double redd[16];
+  const int k = threadIdx.x;
+  float2* g = a.G + chunk_off(b, N);
+  float2 v = make_float2(0.f, 0.f), fo = v;
+  if (k < N) {
+    v = g[(size_t)k * N + u];
+    fo = a.Fo[chunk_off(b, N) + (size_t)k * N + u];
+  }
+  load_twiddles<N>(tw);
+  if (k < N) A[k] = v;
+  __syncthreads();
+  float2* F = fft_lds<N, false>(A, B, 1, tw);
+  float2* G2 = (F == A) ? B : A;
+  double gy = 0.0, gx = 0.0;
+  if (k < N) {
+    const int ky = k < N / 2 ? k : k - N, kx = u < N / 2 ? u : u - N;
+    const float2 fg = F[k];
+    // Re conj(Fg) (i w) Fo = -w Im(conj(Fg) Fo), w = 2 pi k / N; unitary
+    // spectra are the unnormalised ones / N
+    const float2 cf = cmulc(fo, fg);  // Fo conj(Fg)
+    const double im = (double)cf.y / ((double)N * (double)N);
+    gy = -2.0 * M_PI * (double)ky / (double)N * im;
+    gx = -2.0 * M_PI * (double)kx / (double)N * im;
+    G2[k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true>(G2, F, 1, tw);
+  if (k < N) g[(size_t)k * N + u] = H[k];
+  gy = block_sum(gy, redd);
+  gx = block_sum(gx, redd);
+  if (threadIdx.x == 0 && a.subpixel) {
+    a.pos_part[((size_t)b * N + u) * 2] = gy;
+    a.pos_part[((size_t)b * N + u) * 2 + 1] = gx;
+  }
+}
+
+// P7 (rows): inverse row FFT -> S_{-f}(g) row r (object-gradient term)
+template <int N>
+__device__ void adj_p7(const AdjArgs& a, float2* smem) {
+  const int r = blockIdx.x, b = blockIdx.y;
+  float2* tw = smem;
+  float2* A = tw + N;
+  float2* B = A + N;
+  const int c = threadIdx.x;
+  float2* g = a.G + chunk_off(b, N);
+  float2 v = make_float2(0.f, 0.f);
+  if (c < N) v = g[(size_t)r * N + c];
+  load_twiddles<N>(tw);
+  if (c < N) A[c] = v;
+  __syncthreads();
+  float2* R = fft_lds<N, true>(A, B, 1, tw);
+  if (c < N) g[(size_t)r * N + c] = R[c];
+}
+
+#define MRPIE_ADJ_KERNEL(NAME, FN)                       \
+  __global__ __launch_bounds__(256) void NAME(const AdjArgs a) { \
+    extern __shared__ float2 smem[];                     \
+    switch (a.N) {                                       \
+      case 32: FN<32>(a, smem); break;                   \
+      case 64: FN<64>(a, smem); break;                   \
+      case 128: FN<128>(a, smem); break;                 \
+      case 192: FN<192>(a, smem); break;                 \
+      default: FN<256>(a, smem); break;                  \
+    }                                                    \
+  }
+MRPIE_ADJ_KERNEL(k_adj_p1, adj_p1)
+MRPIE_ADJ_KERNEL(k_adj_p2, adj_p2)
+MRPIE_ADJ_KERNEL(k_adj_p3, adj_p3)
+MRPIE_ADJ_KERNEL(k_adj_p4, adj_p4)
+MRPIE_ADJ_KERNEL(k_adj_p5, adj_p5)
+MRPIE_ADJ_KERNEL(k_adj_p6, adj_p6)
+MRPIE_ADJ_KERNEL(k_adj_p7, adj_p7)
+
+// ---------------------------------------------------------------- reductions
+// loss += sum over the chunk's (position, column) partials, in order
+__global__ __launch_bounds__(256) void k_adj_loss(const AdjArgs a, int nb) {
+  __shared__ double red[16];
+  double v = 0.0;
+  const int n = nb * a.N;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += a.loss_part[i];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) *a.loss_acc += v;
+}
+
+// grad_pos[j] = sum over columns of the position partials
+__global__ __launch_bounds__(256) void k_adj_pos(const AdjArgs a, int nb) {
+  __shared__ double red[16];
+  const int b = blockIdx.x;
+  double gy = 0.0, gx = 0.0;
+  for (int u = threadIdx.x; u < a.N; u += blockDim.x) {
+    gy += a.pos_part[((size_t)b * a.N + u) * 2];
+    gx += a.pos_part[((size_t)b * a.N + u) * 2 + 1];
+  }
+  gy = block_sum(gy, red);
+  gx = block_sum(gx, red);
+  if (threadIdx.x == 0) {
+    a.grad_pos[2 * (a.j0 + b)] = a.subpixel ? (float)gy : 0.f;
+    a.grad_pos[2 * (a.j0 + b) + 1] = a.subpixel ? (float)gx : 0.f;
+  }
+}
+
+// grad_P += sum_b (2 chi conj(o))_b over the chunk, in position order
+__global__ __launch_bounds__(256) void k_adj_probe(const AdjArgs a, int nb) {
+  const size_t MNN = (size_t)a.M * a.N * a.N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < MNN; i += (size_t)gridDim.x * blockDim.x) {
+    float2 s = a.grad_probe[i];
+    for (int b = 0; b < nb; ++b) s = cadd(s, a.Psi[(size_t)b * MNN + i]);
+    a.grad_probe[i] = s;
+  }
+}
+
+// grad_O += the chunk's S_{-f}(g) patches at their boxes, in position order.
+// One workgroup per 16 x 16 object tile; it lists the overlapping boxes
+// first, so each pixel visits only those.
+constexpr int kObjTile = 16;
+__global__ __launch_bounds__(256) void k_adj_object(const AdjArgs a, int nb) {
+  __shared__ int lst[kAdjChunk];
+  __shared__ int boxes[kAdjChunk][2];
+  __shared__ int cnt;
+  const int N = a.N;
+  const int ty0 = blockIdx.y * kObjTile, tx0 = blockIdx.x * kObjTile;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int j = a.j0 + b;
+    const int ny = box_corner(a.pos[2 * j], a.H - N, nullptr);
+    const int nx = box_corner(a.pos[2 * j + 1], a.W - N, nullptr);
+    boxes[b][0] = ny;
+    boxes[b][1] = nx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int ny = boxes[b][0], nx = boxes[b][1];
+      if (ny < ty0 + kObjTile && ny + N > ty0 && nx < tx0 + kObjTile && nx + N > tx0) lst[n++] = b;
+    }
+    cnt = n;
+  }
+  __syncthreads();
+  const int y = ty0 + threadIdx.x / kObjTile, x = tx0 + threadIdx.x % kObjTile;
+  if (y >= a.H || x >= a.W) return;
+  float2 s = a.grad_obj[(size_t)y * a.W + x];
+  for (int q = 0; q < cnt; ++q) {
+    const int b = lst[q];
+    const int dy = y - boxes[b][0], dx = x - boxes[b][1];
+    if (dy >= 0 && dy < N && dx >= 0 && dx < N) s = cadd(s, a.G[chunk_off(b, N) + (size_t)dy * N + dx]);
+  }
+  a.grad_obj[(size_t)y * a.W + x] = s;
+}
+
+__global__ void k_adj_zero(float2* p, size_t n, double* d) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_float2(0.f, 0.f);
+  if (d && blockIdx.x == 0 && threadIdx.x == 0) *d = 0.0;
+}
+
+__global__ void k_adj_loss_out(const double* acc, double* out) {
+  if (threadIdx.x == 0) *out = *acc;
+}
+
+// ---------------------------------------------------------------- host
+AdjLayout adj_layout(int N, int M, int J) {
+  AdjLayout L{};
+  const int B = std::max(1, std::min(J, kAdjChunk));
+  const size_t NN = (size_t)N * N;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = ws_align(off + bytes); return o; };
+  L.chunk = B;
+  L.Cp = take((size_t)B * NN * 8);
+  L.Fo = take((size_t)B * NN * 8);
+  L.G = take((size_t)B * NN * 8);
+  L.Psi = take((size_t)B * M * NN * 8);
+  L.loss_part = take((size_t)B * N * 8);
+  L.pos_part = take((size_t)B * N * 16);
+  L.loss_acc = take(16);
+  L.total = off;
+  return L;
+}
+
+int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const float2* probe, const float* pos,
+                const float* intens, double* loss_out, float2* gobj, float2* gprobe, float* gpos, int32_t* status,
+                void* ws, size_t ws_bytes, hipStream_t s) {
+  const int N = pb->N, M = pb->M, J = pb->J;
+  const AdjLayout L = adj_layout(N, M, J);
+  if (!ws || ws_bytes < L.total) return fail(MRPIE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  int rc = launch_init_twiddles(s);
+  if (rc) return rc;
+  char* w = (char*)ws;
+  const bool grads = gobj != nullptr;
+  AdjArgs a{};
+  a.H = pb->H; a.W = pb->W; a.N = N; a.M = M; a.J = J; a.subpixel = subpixel;
+  a.obj = obj; a.probe = probe; a.pos = pos; a.I = intens; a.status = status;
+  a.Cp = (float2*)(w + L.Cp); a.Fo = (float2*)(w + L.Fo); a.G = (float2*)(w + L.G); a.Psi = (float2*)(w + L.Psi);
+  a.loss_part = (double*)(w + L.loss_part); a.pos_part = (double*)(w + L.pos_part);
+  a.loss_acc = (double*)(w + L.loss_acc);
+  a.grad_obj = gobj; a.grad_probe = gprobe; a.grad_pos = gpos;
+  hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, s, (float2*)nullptr, (size_t)0, a.loss_acc);
+  if (grads) {
+    hipLaunchKernelGGL(k_adj_zero, dim3(2048), dim3(256), 0, s, gobj, (size_t)pb->H * pb->W, (double*)nullptr);
+    hipLaunchKernelGGL(k_adj_zero, dim3(256), dim3(256), 0, s, gprobe, (size_t)M * N * N, (double*)nullptr);
+  }
+  const size_t l1 = (size_t)3 * N * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
+  if (lm1 > 65536) {
+    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
+    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p4, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
+    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p5, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
+  }
+  for (int j0 = 0; j0 < J; j0 += L.chunk) {
+    const int nb = std::min(L.chunk, J - j0);
+    a.j0 = j0;
+    const dim3 g(N, nb), blk(256);
+    {
+      TimingScope ts(TK_ADJ, s);
+      hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_p2, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
+      hipLaunchKernelGGL(k_adj_p4, g, blk, lm, s, a);
+    }
+    hipLaunchKernelGGL(k_adj_loss, dim3(1), blk, 0, s, a, nb);
+    if (grads) {
+      hipLaunchKernelGGL(k_adj_p5, g, blk, lm, s, a);
+      hipLaunchKernelGGL(k_adj_p6, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_p7, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_pos, dim3(nb), blk, 0, s, a, nb);
+      hipLaunchKernelGGL(k_adj_probe, dim3(512), blk, 0, s, a, nb);
+      hipLaunchKernelGGL(k_adj_object, dim3((pb->W + kObjTile - 1) / kObjTile, (pb->H + kObjTile - 1) / kObjTile),
+                         blk, 0, s, a, nb);
+    }
+  }
+  if (loss_out) hipLaunchKernelGGL(k_adj_loss_out, dim3(1), dim3(64), 0, s, (const double*)a.loss_acc, loss_out);
+  MRPIE_HIP(hipGetLastError());
+  return MRPIE_OK;
+}
+
+}  // namespace mrpie
+
+using namespace mrpie;
+
+extern "C" {
+
+int mrpie_grad_workspace_size(const mrpie_problem* pb, size_t* bytes) {
+  if (!pb || !bytes) return fail(MRPIE_EINVAL, "null argument");
+  if (n_index(pb->N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", pb->N);
+  if (pb->M < 1 || pb->M > MRPIE_MAX_MODES || pb->J < 1 || pb->H < pb->N || pb->W < pb->N)
+    return fail(pb->M > MRPIE_MAX_MODES ? MRPIE_EUNSUPPORTED : MRPIE_EINVAL, "bad problem shape");
+  *bytes = adj_layout(pb->N, pb->M, pb->J).total;
+  return MRPIE_OK;
+}
+
+static int adj_check(const mrpie_problem* pb, int subpixel, const void* obj, const void* probe, const float* pos,
+                     const float* intens) {
+  size_t n;
+  int rc = mrpie_grad_workspace_size(pb, &n);
+  if (rc) return rc;
+  if (subpixel != 0 && subpixel != 1) return fail(MRPIE_EINVAL, "subpixel must be 0 or 1");
+  if ((long long)pb->H * pb->W >= (1LL << 31)) return fail(MRPIE_EINVAL, "object too large");
+  if (!obj || !probe || !pos || !intens) return fail(MRPIE_EINVAL, "null array pointer");
+  return MRPIE_OK;
+}
+
+int mrpie_loss(const mrpie_problem* pb, int32_t subpixel, const void* obj, const void* probe, const float* pos,
+               const float* intens, double* loss_out, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  int rc = adj_check(pb, subpixel, obj, probe, pos, intens);
+  if (rc) return rc;
+  if (!loss_out) return fail(MRPIE_EINVAL, "loss_out is NULL");
+  return run_adjoint(pb, subpixel, (const float2*)obj, (const float2*)probe, pos, intens, loss_out, nullptr, nullptr,
+                     nullptr, status, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int mrpie_adjoint(const mrpie_problem* pb, int32_t subpixel, const void* obj, const void* probe, const float* pos,
+                  const float* intens, double* loss_out, void* grad_obj, void* grad_probe, float* grad_pos,
+                  int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  int rc = adj_check(pb, subpixel, obj, probe, pos, intens);
+  if (rc) return rc;
+  if (!grad_obj || !grad_probe || !grad_pos) return fail(MRPIE_EINVAL, "null gradient pointer");
+  return run_adjoint(pb, subpixel, (const float2*)obj, (const float2*)probe, pos, intens, loss_out,
+                     (float2*)grad_obj, (float2*)grad_probe, grad_pos, status, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -167,7 +167,7 @@ int mrpie_timing_read(double* avg_ms, int64_t* count, int32_t nkinds) {
 }
 
 int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream) {
-  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", N);
+  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
   if (B < 0) return fail(MRPIE_EINVAL, "B=%d < 0", B);
   if (B == 0) return MRPIE_OK;
   if (!data) return fail(MRPIE_EINVAL, "data is NULL");
@@ -176,6 +176,7 @@ int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream) 
   if (rc) return rc;
   float2* d = (float2*)data;
   switch (N) {
+    case 32: return fft2_impl<32>(B, d, inverse, s);
     case 64: return fft2_impl<64>(B, d, inverse, s);
     case 128: return fft2_impl<128>(B, d, inverse, s);
     case 192: return fft2_impl<192>(B, d, inverse, s);

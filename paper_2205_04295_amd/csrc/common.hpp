@@ -29,6 +29,7 @@ inline int n_index(int N) {
     case 128: return 1;
     case 192: return 2;
     case 256: return 3;
+    case 32: return 4;
     default: return -1;
   }
 }
@@ -36,20 +37,22 @@ inline int n_index(int N) {
 // Roots of unity w_N^e = exp(-2 pi i e / N), e < N, for the four sizes;
 // written by k_init_twiddles in double precision and rounded once.  Each
 // translation unit holds its own copy (no relocatable device code).
-static __device__ float2 g_tw[4][256];
+static __device__ float2 g_tw[5][256];
+static __device__ double2 g_tw64[5][256];
 
 static __global__ void k_init_twiddles() {
   const int idx = blockIdx.x;
-  const int N = idx == 0 ? 64 : idx == 1 ? 128 : idx == 2 ? 192 : 256;
+  const int N = idx == 0 ? 64 : idx == 1 ? 128 : idx == 2 ? 192 : idx == 3 ? 256 : 32;
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
     double s, c;
     sincospi(-2.0 * (double)e / (double)N, &s, &c);
     g_tw[idx][e] = make_float2((float)c, (float)s);
+    g_tw64[idx][e] = make_double2(c, s);
   }
 }
 
 static inline int launch_init_twiddles(hipStream_t s) {
-  hipLaunchKernelGGL(k_init_twiddles, dim3(4), dim3(256), 0, s);
+  hipLaunchKernelGGL(k_init_twiddles, dim3(5), dim3(256), 0, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_init_twiddles");
   return MRPIE_OK;
@@ -58,8 +61,13 @@ static inline int launch_init_twiddles(hipStream_t s) {
 // Copy the N-entry twiddle table to LDS.
 template <int N>
 __device__ __forceinline__ void load_twiddles(float2* s_tw) {
-  constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : 3;
+  constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : N == 256 ? 3 : 4;
   for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw[idx][i];
+}
+template <int N>
+__device__ __forceinline__ void load_twiddles(double2* s_tw) {
+  constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : N == 256 ? 3 : 4;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw64[idx][i];
 }
 
 // Workgroup reductions (64-wide waves).
@@ -123,7 +131,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
 // launch of a timed kernel class is bracketed by a HIP event pair on its
 // stream; mrpie_timing_read() averages the recorded durations.
-enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_ADJ = 3, TK_COUNT = 8 };
+enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_COUNT = 8 };
 struct TimingScope {
   TimingScope(int kind, hipStream_t s);
   ~TimingScope();

@@ -33,6 +33,7 @@
 #include <cmath>
 #include <vector>
 
+#include "register.hpp"
 #include "sweep.hpp"
 
 namespace mrpie {
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
+    case 32: rows_body<32, R4>(a.c, jb, t, smem); break;
     case 64: rows_body<64, R4>(a.c, jb, t, smem); break;
     case 128: rows_body<128, R4>(a.c, jb, t, smem); break;
     case 192: rows_body<192, R4>(a.c, jb, t, smem); break;
@@ -330,6 +332,7 @@ __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
+    case 32: cols_body<32, R4>(jb, t, smem); break;
     case 64: cols_body<64, R4>(jb, t, smem); break;
     case 128: cols_body<128, R4>(jb, t, smem); break;
     case 192: cols_body<192, R4>(jb, t, smem); break;
@@ -397,8 +400,9 @@ __global__ void k_probe_back(const LaunchArgs a) {
 
 // ------------------------------------------------------------ tuning
 // Launch shapes of the sweep, per (N, batch class): FFT radix plan of each
-// pass and threads per row workgroup.  Defaults favour latency (radix 4,
-// 512 threads); mrpie_autotune measures the alternatives on the device.
+// pass and threads per row workgroup.  The default (radix 8 in both passes,
+// 256 threads) was the fastest measured for 256^2 x 3 on MI355X; the
+// autotuner measures the alternatives on the device for any (N, M, batch).
 static Tuning g_tune[4][2];
 static bool g_tune_set[4][2];
 
@@ -408,7 +412,7 @@ Tuning get_tuning(int N, int M, int nb) {
   (void)M;
   const int ni = n_index(N), bc = batch_class(nb);
   if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
-  return Tuning{4, 4, 512};
+  return Tuning{8, 8, 256};
 }
 
 void set_tuning(int N, int nb, const Tuning& t) {
@@ -421,6 +425,27 @@ void set_tuning(int N, int nb, const Tuning& t) {
 // ------------------------------------------------------------ host driver
 static size_t rows_lds(int N, int M) { return (size_t)(N + N + 6 * M * N) * 8; }
 static size_t cols_lds(int N, int M) { return (size_t)(N + 2 * M * N) * 8; }
+
+void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s) {
+  size_t lc = 0;
+  for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M));
+  const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+  TimingScope ts(TK_COLS, s);
+  if (tu.cols_radix == 8) hipLaunchKernelGGL(k_cols<false>, dim3(maxN, nb), dim3(256), lc, s, a, t);
+  else hipLaunchKernelGGL(k_cols<true>, dim3(maxN, nb), dim3(256), lc, s, a, t);
+}
+
+void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_err, dim3(8, nb), dim3(256), 0, s, a);
+}
+
+void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s) {
+  ErrOut eo{};
+  for (int b = 0; b < nb; ++b) eo.p[b] = err_out ? err_out[b] : nullptr;
+  hipLaunchKernelGGL(k_probe_back, dim3(64, nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_finish, dim3(1, nb), dim3(256), 0, s, a, eo);
+}
 
 int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
   int rc = launch_init_twiddles(s);
@@ -470,6 +495,73 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
   return MRPIE_OK;
 }
 
+// Workspace of mrpie_rpie: the sweep layout, then (refinement only) the
+// recorded patch pairs, shifts, peaks and the registration workspace.
+struct RefineLayout {
+  size_t ref, mov, shift, peak, reg, total;
+};
+
+static RefineLayout refine_layout(const mrpie_problem* pb, const mrpie_params* pr) {
+  RefineLayout R{};
+  size_t off = ws_layout(pb->N, pb->M, pr->iterations).total;
+  auto take = [&](size_t bytes) { size_t o = off; off = ws_align(off + bytes); return o; };
+  if (pr->refine) {
+    const size_t NN = (size_t)pb->N * pb->N;
+    R.ref = take((size_t)pb->J * NN * 8);
+    R.mov = take((size_t)pb->J * NN * 8);
+    R.shift = take((size_t)pb->J * 8);
+    R.peak = take((size_t)pb->J * 16);
+    R.reg = take(reg_layout(pb->N, pb->J, pr->upsample).total);
+  }
+  R.total = off;
+  return R;
+}
+
+size_t rpie_ws_total(const mrpie_problem* pb, const mrpie_params* pr) { return refine_layout(pb, pr).total; }
+
+int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr, float* adam, float* err_out,
+                       hipStream_t s) {
+  mrpie_problem pb{jb.H, jb.W, jb.N, jb.M, jb.J};
+  const RefineLayout R = refine_layout(&pb, pr);
+  // k_cols below belongs to this translation unit: its twiddle table
+  int rc0 = launch_init_twiddles(s);
+  if (rc0) return rc0;
+  LaunchArgs la{};
+  la.c = c;
+  la.njobs = 1;
+  la.job[0] = jb;
+  launch_zero_err(la, 1, s);
+  SubpixelExtra ex{pr->subpixel, nullptr, nullptr, pr->refine_start};
+  int rc;
+  if (!pr->refine) {
+    rc = run_sweep_subpixel(c, jb, ex, 0, jb.T, true, true, s);
+    if (rc) return rc;
+  } else {
+    ex.reg_ref = (float2*)(jb.ws + R.ref);
+    ex.reg_mov = (float2*)(jb.ws + R.mov);
+    float* shift = (float*)(jb.ws + R.shift);
+    int32_t* peak = (int32_t*)(jb.ws + R.peak);
+    const size_t reg_bytes = reg_layout(jb.N, jb.J, pr->upsample).total;
+    for (int it = 0; it < jb.T; ++it) {
+      rc = run_sweep_subpixel(c, jb, ex, it, 1, true, true, s);
+      if (rc) return rc;
+      const int it_abs = pr->iter_offset + it;
+      if (it_abs >= pr->refine_start) {
+        rc = run_register(jb.N, jb.J, ex.reg_ref, ex.reg_mov, pr->upsample, pr->xcorr_norm, shift, peak,
+                          jb.ws + R.reg, reg_bytes, s);
+        if (rc) return rc;
+        rc = launch_adam(jb.J, (float*)jb.pos, adam, shift, it_abs - pr->refine_start + 1, pr, jb.H - jb.N,
+                         jb.W - jb.N, s);
+        if (rc) return rc;
+      }
+    }
+  }
+  float* eo[1] = {err_out};
+  launch_finish(la, 1, eo, s);
+  MRPIE_HIP(hipGetLastError());
+  return MRPIE_OK;
+}
+
 }  // namespace mrpie
 
 using namespace mrpie;
@@ -478,7 +570,7 @@ extern "C" {
 
 int mrpie_validate(const mrpie_problem* pb, const mrpie_params* pr) {
   if (!pb || !pr) return fail(MRPIE_EINVAL, "null problem or params");
-  if (n_index(pb->N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", pb->N);
+  if (n_index(pb->N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", pb->N);
   if (pb->M < 1) return fail(MRPIE_EINVAL, "M=%d < 1", pb->M);
   if (pb->M > MRPIE_MAX_MODES) return fail(MRPIE_EUNSUPPORTED, "M=%d > %d", pb->M, MRPIE_MAX_MODES);
   if (pb->J < 1) return fail(MRPIE_EINVAL, "J=%d < 1", pb->J);
@@ -501,7 +593,6 @@ int mrpie_validate(const mrpie_problem* pb, const mrpie_params* pr) {
       return fail(MRPIE_EINVAL, "Adam betas must be in [0,1)");
     if (!(pr->adam_eps > 0.f) || !finite(pr->adam_lr)) return fail(MRPIE_EINVAL, "bad Adam lr/eps");
   }
-  if (pr->subpixel || pr->refine) return fail(MRPIE_EUNSUPPORTED, "subpixel / refine not built in this library");
   return MRPIE_OK;
 }
 
@@ -509,7 +600,7 @@ int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t
   int rc = mrpie_validate(pb, pr);
   if (rc) return rc;
   if (!bytes) return fail(MRPIE_EINVAL, "bytes is NULL");
-  *bytes = ws_layout(pb->N, pb->M, pr->iterations).total;
+  *bytes = rpie_ws_total(pb, pr);
   return MRPIE_OK;
 }
 
@@ -520,18 +611,20 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
   if (rc) return rc;
   if (!obj || !probe || !pos || !intens) return fail(MRPIE_EINVAL, "null array pointer");
   if (pr->refine && !adam) return fail(MRPIE_EINVAL, "adam state is NULL with refine = 1");
-  const WsLayout L = ws_layout(pb->N, pb->M, pr->iterations);
-  if (!ws || ws_bytes < L.total) return fail(MRPIE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  const size_t need = rpie_ws_total(pb, pr);
+  if (!ws || ws_bytes < need) return fail(MRPIE_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   if (pr->iterations == 0) return MRPIE_OK;
+  hipStream_t s = (hipStream_t)stream;
   Common c{pr->alpha_obj, pr->alpha_probe, pr->beta, pr->gamma, pr->iter_offset, pr->probe_update_start};
   JobRec jb{(float2*)obj, (float2*)probe, pos, intens, (char*)ws, status,
             pb->H, pb->W, pb->N, pb->M, pb->J, pr->iterations};
   float* eo[1] = {err_out};
-  return run_sweep(c, &jb, 1, eo, (hipStream_t)stream);
+  if (!pr->subpixel && !pr->refine) return run_sweep(c, &jb, 1, eo, s);
+  return run_refining_sweep(c, jb, pr, adam, err_out, s);
 }
 
 int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
-  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", N);
+  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
   if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
   if ((t->rows_radix != 4 && t->rows_radix != 8) || (t->cols_radix != 4 && t->cols_radix != 8))
     return fail(MRPIE_EINVAL, "radix must be 4 or 8");
@@ -541,7 +634,7 @@ int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
 }
 
 int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
-  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {64,128,192,256}", N);
+  if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
   if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
   const Tuning u = get_tuning(N, 1, batched ? 2 : 1);
   t->rows_radix = u.rows_radix;

@@ -34,7 +34,7 @@ struct LaunchArgs {
 
 // Workspace layout of one job; identical on host and device.
 struct WsLayout {
-  size_t psi[2], patch[2], probe1, pmax[2], omax[2], box[2], err, isum, total;
+  size_t psi[2], patch[2], probe1, pmax[2], omax[2], box[2], err, isum, cb, db, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~size_t(255); }
@@ -59,6 +59,8 @@ __host__ __device__ inline WsLayout ws_layout(int N, int M, int T) {
   MRPIE_TAKE(L.box[1], 16)
   MRPIE_TAKE(L.err, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)
   MRPIE_TAKE(L.isum, (size_t)kIsumParts * 8)
+  MRPIE_TAKE(L.cb, NN * 8)   // subpixel path: shifted-crop spectra
+  MRPIE_TAKE(L.db, NN * 8)   // subpixel path: object-update spectra
 #undef MRPIE_TAKE
   L.total = off;
   return L;
@@ -72,6 +74,21 @@ struct Tuning {
 };
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);
+
+// Subpixel / refining sweep (six launches per position).  `reg_ref`,
+// `reg_mov` ([J][N][N] each) receive the patch before and after its update
+// when `record` is set.
+struct SubpixelExtra {
+  int subpixel;      // 0: fractions forced to 0 (refinement on integer crops)
+  float2* reg_ref;
+  float2* reg_mov;
+  int record_start;  // absolute iteration from which pairs are recorded
+};
+int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
+                       bool tail, hipStream_t s);
+size_t rpie_ws_total(const mrpie_problem* pb, const mrpie_params* pr);
+int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr, float* adam, float* err_out,
+                       hipStream_t s);
 
 // Host driver: runs `T` iterations (per job) of the sweep for every job in
 // `jobs` (any mix of N and M), lock-step by position: tick t performs the

@@ -86,3 +86,28 @@ def test_workspace_too_small_rejected(lib):
     rc = lib.mrpie_rpie(C.byref(pb), C.byref(prm), fake, fake, fake, None, fake, None, None, fake,
                         C.c_size_t(16), None)
     assert rc == _abi.MRPIE_EWORKSPACE
+
+
+def test_register_and_adam_argument_checks(lib):
+    n = C.c_size_t(0)
+    assert lib.mrpie_register_workspace_size(256, 1600, 100, C.byref(n)) == 0 and n.value > 0
+    assert lib.mrpie_register_workspace_size(96, 4, 100, C.byref(n)) == _abi.MRPIE_EUNSUPPORTED
+    assert lib.mrpie_register_workspace_size(64, 4, 0, C.byref(n)) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_register(64, 0, None, None, 100, 1, None, None, None, 0, None) == 0
+    assert lib.mrpie_register(64, 2, None, None, 100, 1, None, None, None, 0, None) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_register(64, 2, None, None, 100, 3, None, None, None, 0, None) == _abi.MRPIE_EINVAL
+    prm = make_params(adam_b1=1.0)
+    assert lib.mrpie_adam(4, C.byref(prm), 10, 10, None, None, None, 1, None) == _abi.MRPIE_EINVAL
+    prm = make_params()
+    assert lib.mrpie_adam(4, C.byref(prm), 10, 10, None, None, None, 0, None) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_adam(0, C.byref(prm), 10, 10, None, None, None, 1, None) == 0
+
+
+def test_tuning_round_trip(lib):
+    t = _abi.Tuning(8, 4, 256)
+    assert lib.mrpie_set_tuning(128, 1, C.byref(t)) == 0
+    u = _abi.Tuning()
+    assert lib.mrpie_get_tuning(128, 1, C.byref(u)) == 0
+    assert (u.rows_radix, u.cols_radix, u.rows_threads) == (8, 4, 256)
+    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(5, 4, 256))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(100, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
