@@ -138,13 +138,16 @@ def measure_refine(api, torch, dev, args):
         ws = api.rpie(obj, probe, pos, I, adam=adam, workspace=ws, iterations=1, iter_offset=it, **prm)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    after = rms(pos.cpu().numpy().astype(np.float64))
+    pos_after = pos.cpu().numpy().astype(np.float64)
+    after = rms(pos_after)
+    moved = float(np.mean(np.any(np.abs(pos_after - w.pos0) > 0, axis=1)))
     return {"workload": "spiral256x3 with N(0, 3 px) position errors, subpixel Fourier moves, XCORR_A "
                         "registration (upsample 100, phase correlation) + Adam (lr 0.5) every iteration",
             "iterations": T, "value": round(J * T / el, 1), "unit": "positions*iter/s",
             "ms_per_iter": round(el * 1e3 / T, 3),
             "pos_rms_px_before": [round(x, 4) for x in before], "pos_rms_px_after": [round(x, 4) for x in after],
-            "rms_note": "[raw, mean-offset removed]", "datagen_s": round(gen, 1)}
+            "rms_note": "[raw, mean-offset removed]", "positions_moved_frac": round(moved, 4),
+            "datagen_s": round(gen, 1)}
 
 
 def measure_adjoint(api, torch, dev, obj, probe, pos, I, args):

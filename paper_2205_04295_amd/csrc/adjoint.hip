@@ -458,9 +458,9 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   }
   const size_t l1 = (size_t)3 * N * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
   if (lm1 > 65536) {
-    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
-    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p4, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
-    MRPIE_HIP(hipFuncSetAttribute((const void*)k_adj_p5, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm1));
+    MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
+    MRPIE_HIP(ensure_lds((const void*)k_adj_p4, lm1));
+    MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm1));
   }
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);

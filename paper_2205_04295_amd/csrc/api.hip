@@ -2,6 +2,8 @@
 // the FFT / modulus test hooks.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "common.hpp"
 
@@ -27,6 +29,19 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
   set_error("HIP error '%s' in %s", hipGetErrorString(e), what);
   return MRPIE_EDEVICE;
+}
+
+// ------------------------------------------------------------ LDS limits
+hipError_t ensure_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kernel);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done[kernel] = bytes;
+  return e;
 }
 
 // ------------------------------------------------------------ timing

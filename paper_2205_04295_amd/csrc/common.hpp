@@ -127,6 +127,10 @@ __device__ __forceinline__ int xcd_unit(int b, int nunits) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Raise a kernel's dynamic-LDS limit once to at least `bytes` (host-side
+// attribute; done outside any stream capture the first time a size is seen).
+hipError_t ensure_lds(const void* kernel, size_t bytes);
+
 // ---------------------------------------------------------------- timing
 // Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
 // launch of a timed kernel class is bracketed by a HIP event pair on its

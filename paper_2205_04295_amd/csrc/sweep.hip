@@ -430,6 +430,7 @@ void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t 
   size_t lc = 0;
   for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M));
   const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+  (void)ensure_lds(tu.cols_radix == 8 ? (const void*)k_cols<false> : (const void*)k_cols<true>, lc);
   TimingScope ts(TK_COLS, s);
   if (tu.cols_radix == 8) hipLaunchKernelGGL(k_cols<false>, dim3(maxN, nb), dim3(256), lc, s, a, t);
   else hipLaunchKernelGGL(k_cols<true>, dim3(maxN, nb), dim3(256), lc, s, a, t);
@@ -470,8 +471,8 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
     const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
     const void* kr = tu.rows_radix == 8 ? (const void*)k_rows<false> : (const void*)k_rows<true>;
     const void* kc = tu.cols_radix == 8 ? (const void*)k_cols<false> : (const void*)k_cols<true>;
-    if (lr > 65536) MRPIE_HIP(hipFuncSetAttribute(kr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr));
-    if (lc > 65536) MRPIE_HIP(hipFuncSetAttribute(kc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+    MRPIE_HIP(ensure_lds(kr, lr));
+    MRPIE_HIP(ensure_lds(kc, lc));
     const dim3 blk(256), rblk(tu.rows_threads);
     hipLaunchKernelGGL(k_zero_err, dim3(8, nb), blk, 0, s, a);
     if (maxTot == 0) continue;

@@ -378,8 +378,8 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
   const size_t le = (size_t)(N + 2 * (M + 1) * N) * 8;
   const size_t lu = (size_t)(N + 2 * M * N) * 8;
   const size_t lr = (size_t)(N + 2 * N) * 8;
-  if (le > 65536) MRPIE_HIP(hipFuncSetAttribute((const void*)k_sp_exit, hipFuncAttributeMaxDynamicSharedMemorySize, (int)le));
-  if (lu > 65536) MRPIE_HIP(hipFuncSetAttribute((const void*)k_sp_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lu));
+  MRPIE_HIP(ensure_lds((const void*)k_sp_exit, le));
+  MRPIE_HIP(ensure_lds((const void*)k_sp_update, lu));
   const dim3 g(N), blk(256);
   const int t0 = it0 * jb.J, t1 = (it0 + iters) * jb.J;
   for (int t = t0; t < t1; ++t) {

@@ -59,24 +59,30 @@ def test_subpixel_multi_iteration():
 def test_refinement_one_iteration(subpixel):
     """One refining iteration: the sweep itself matches the oracle; the
     measured shifts (recovered from Adam's first moment, m = (1-b1) g at
-    t = 1) agree with the oracle's to the window spacing; the positions move
-    by lr * sign(g)."""
+    t = 1) agree with the oracle's to the window spacing; where the shifts
+    agree the positions move identically (by lr * sign(g)).  upsample = 1000
+    so that the shifts of this short run are mostly non-zero (at 100 they
+    round to zero)."""
     w = wl.small_case(111, 384, 128, 2, 12, subpixel=True, name="refine")
     w.pos0 = (w.pos_true + np.random.default_rng(3).normal(0, 2.0, size=w.pos_true.shape)).astype(np.float32)
     w.pos0 = np.clip(w.pos0, 0, 384 - 128).astype(np.float32)
-    prm = dict(w.params, iterations=1, subpixel=subpixel, refine=1, upsample=100, xcorr_norm=1,
+    up = 1000
+    prm = dict(w.params, iterations=1, subpixel=subpixel, refine=1, upsample=up, xcorr_norm=1,
                adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
     adam0 = np.zeros((w.pos0.shape[0], 4), np.float32)
     g = run_gpu(w, prm, adam=adam0)
     o = run_oracle(w, prm)
     assert rel_l2(g["O"], o["O"]) < 1e-4 and rel_l2(g["P"], o["P"]) < 1e-4
-    g_gpu = g["adam"][:, :2] / (1 - 0.9)
+    g_gpu = g["adam"][:, :2].astype(np.float64) / (1 - np.float32(0.9))
     g_orc = o["adam"][:, :2] / (1 - 0.9)
+    assert np.mean(g_orc != 0) > 0.5                      # the run does exercise the controller
     diff = np.abs(g_gpu - g_orc)
-    print("max shift difference", diff.max())
-    assert np.mean(diff <= 0.0101) >= 0.9 and diff.max() < 0.1
-    big = np.abs(g_orc) > 0.02
-    assert np.allclose(g["pos"][big], o["pos"][big], atol=1e-3)
+    print("shifts gpu", np.round(g_gpu[:4], 4).tolist(), "oracle", np.round(g_orc[:4], 4).tolist())
+    assert np.mean(diff <= 1.01 / up) >= 0.75 and diff.max() < 0.01
+    same = np.abs(g_gpu - g_orc) < 0.5 / up
+    moved = np.abs(g["pos"] - w.pos0) > 0.4
+    assert np.any(moved)
+    assert np.allclose(g["pos"][same], o["pos"][same], atol=1e-3)
 
 
 FRESH = r"""
