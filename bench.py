@@ -24,6 +24,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Per-launch HBM traffic of the plain sweep's kernels from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+# counter reads for a plain 256 MiB device copy (profiles/
+# k_rows_spiral256x3_counters.md).  Valid only for the kernel sources they
+# were taken on: bench reports traffic = null when the sources differ.
+COUNTERS = {
+    "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
+                "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
+    "sha256": None,
+    "fetch_factor": 2.000, "write_factor": 1.000,
+    "k_rows": {"fetch_kib": 3371.4, "write_kib": 4097.7},
+    "k_cols": {"fetch_kib": 1012.0, "write_kib": 1538.0},
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNTERS["sources"]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel):
+    """Scaled HBM bytes per launch of `kernel`, or None if not measured on
+    the current kernel sources."""
+    c = COUNTERS.get(kernel)
+    if c is None or COUNTERS["sha256"] != kernel_sources_sha256():
+        return None
+    return 1024.0 * (c["fetch_kib"] * COUNTERS["fetch_factor"] + c["write_kib"] * COUNTERS["write_factor"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -252,8 +284,24 @@ def main():
     kt = api.timing_read()
     api.timing_enable(0)
 
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = J * args.steps / elapsed
+    # the same iteration recorded once as a HIP graph and replayed per step
+    from paper_2205_04295_amd import graph as hgraph
+    g, ws = hgraph.capture_plain(obj, probe, pos, I, workspace=ws, err=err, iterations=1, **prm)
+    g.replay()
+    torch.cuda.synchronize()
+    t_g = time.perf_counter()
+    for k in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    elapsed_graph = time.perf_counter() - t_g
+
+    eager = {"value": round(J * args.steps / elapsed, 1), "ms_per_step": round(elapsed * 1e3 / args.steps, 4)}
+    graph_mode = {"value": round(J * args.steps / elapsed_graph, 1),
+                  "ms_per_step": round(elapsed_graph * 1e3 / args.steps, 4)}
+    use_graph = elapsed_graph < elapsed
+    el = elapsed_graph if use_graph else elapsed
+    ms_per_step = el * 1e3 / args.steps
+    value = J * args.steps / el
     rows_b, cols_b = algorithmic_bytes(N, M)
     per_launch = {"k_rows": rows_b, "k_cols": cols_b}
     # dominant kernel: largest total time per step (one launch of each per position)
@@ -302,12 +350,15 @@ def main():
                    "positions": J, "N": N, "M": M, "object": list(w.O0.shape),
                    "params": {k: v for k, v in w.params.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
                      "kernel": dom, "kernel_avg_us": round(dom_ms * 1e3, 3),
                      "algorithmic_bytes_per_launch": per_launch[dom],
                      "launches_timed": int(kt[dom][1])},
         "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
         "path_algorithmic_GBs": round(path_gbs, 1),
+        "launch_mode": "hip graph replay of one iteration" if use_graph else "eager launches",
+        "eager": eager,
+        "graph": graph_mode,
         "batched": batched,
         "refine": refine,
         "adjoint": adjoint,

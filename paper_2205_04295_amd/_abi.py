@@ -99,6 +99,12 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch (when present) carries its own HIP runtime: load it first so the
+    # library binds to the same runtime instead of bringing a second one
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2205_04295_amd.build` "
                           "or __graft_entry__.build()")

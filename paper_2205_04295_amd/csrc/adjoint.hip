@@ -466,13 +466,10 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     const dim3 g(N, nb), blk(256);
-    {
-      TimingScope ts(TK_ADJ, s);
-      hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
-      hipLaunchKernelGGL(k_adj_p2, g, blk, l1, s, a);
-      hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
-      hipLaunchKernelGGL(k_adj_p4, g, blk, lm, s, a);
-    }
+    hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
+    hipLaunchKernelGGL(k_adj_p2, g, blk, l1, s, a);
+    hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
+    launch_k(TK_ADJ, k_adj_p4, g, blk, lm, s, a);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), blk, 0, s, a, nb);
     if (grads) {
       hipLaunchKernelGGL(k_adj_p5, g, blk, lm, s, a);

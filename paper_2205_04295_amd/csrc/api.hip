@@ -58,17 +58,16 @@ struct Timing {
 Timing g_timing;
 }  // namespace
 
-TimingScope::TimingScope(int kind, hipStream_t s) : slot(-1), stream(s) {
+TimedLaunch timing_slot(int kind) {
   Timing& T = g_timing;
-  if (T.stride <= 0) return;
-  if ((T.seen[kind]++ % T.stride) != 0 || T.used >= kEvPairs) return;
-  slot = T.used++;
+  TimedLaunch t;
+  if (T.stride <= 0) return t;
+  if ((T.seen[kind]++ % T.stride) != 0 || T.used >= kEvPairs) return t;
+  const int slot = T.used++;
   T.kind[slot] = kind;
-  if (hipEventRecord(T.ev[2 * slot], s) != hipSuccess) slot = -1;
-}
-
-TimingScope::~TimingScope() {
-  if (slot >= 0) (void)hipEventRecord(g_timing.ev[2 * slot + 1], stream);
+  t.start = T.ev[2 * slot];
+  t.stop = T.ev[2 * slot + 1];
+  return t;
 }
 
 // ------------------------------------------------------------ FFT test hook

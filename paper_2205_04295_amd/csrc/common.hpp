@@ -1,6 +1,7 @@
 // Shared host/device helpers of the mrpie library (gfx950).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdarg>
 #include <cstdint>
@@ -133,14 +134,20 @@ hipError_t ensure_lds(const void* kernel, size_t bytes);
 
 // ---------------------------------------------------------------- timing
 // Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
-// launch of a timed kernel class is bracketed by a HIP event pair on its
-// stream; mrpie_timing_read() averages the recorded durations.
+// launch of a timed kernel class is launched with hipExtLaunchKernelGGL and
+// a start / stop event pair, so the events carry that dispatch's own start
+// and end time on its stream; mrpie_timing_read() averages them.
 enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_COUNT = 8 };
-struct TimingScope {
-  TimingScope(int kind, hipStream_t s);
-  ~TimingScope();
-  int slot;
-  hipStream_t stream;
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
 };
+TimedLaunch timing_slot(int kind);
+
+template <typename K, typename... A>
+inline void launch_k(int kind, K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+  const TimedLaunch t = timing_slot(kind);
+  if (t.start) hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, t.start, t.stop, 0u, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
 
 }  // namespace mrpie

@@ -388,19 +388,12 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
     a.mov = mov + (size_t)b0 * N * N;
     a.shift = shift + 2 * (size_t)b0;
     a.peak = peak + 4 * (size_t)b0;
-    {
-      TimingScope ts(TK_REG, s);
-      hipLaunchKernelGGL(k_reg_rows<N>, dim3(N, nb, 2), dim3(256), 0, s, a);
-      hipLaunchKernelGGL(k_reg_cols<N>, dim3(N, nb), dim3(256), 0, s, a);
-      hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N, nb), dim3(256), 0, s, a);
-      hipLaunchKernelGGL(k_reg_s0, dim3(nb), dim3(256), 0, s, a, N);
-    }
-    {
-      TimingScope ts(TK_GEMM, s);
-      hipLaunchKernelGGL(k_reg_gemm1<N>, dim3((N + G1_TX - 1) / G1_TX, (U + G1_TU - 1) / G1_TU, nb), dim3(256), 0,
-                         s, a);
-      hipLaunchKernelGGL(k_reg_gemm2<N>, dim3(gt, gt, nb), dim3(256), 0, s, a);
-    }
+    hipLaunchKernelGGL(k_reg_rows<N>, dim3(N, nb, 2), dim3(256), 0, s, a);
+    launch_k(TK_REG, k_reg_cols<N>, dim3(N, nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N, nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reg_s0, dim3(nb), dim3(256), 0, s, a, N);
+    launch_k(TK_GEMM, k_reg_gemm1<N>, dim3((N + G1_TX - 1) / G1_TX, (U + G1_TU - 1) / G1_TU, nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reg_gemm2<N>, dim3(gt, gt, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_final, dim3((nb + 63) / 64), dim3(64), 0, s, a, gt * gt);
   }
   MRPIE_HIP(hipGetLastError());

@@ -41,9 +41,8 @@ namespace mrpie {
 // select one of a pair without dynamic indexing (keeps the layout in SGPRs)
 __device__ __forceinline__ size_t pick(const size_t (&a)[2], int i) { return i ? a[1] : a[0]; }
 
-template <int N, bool R4>
+template <int N, bool R4, int MM>
 __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES;
   const int M = jb.M;
   const int total = jb.J * jb.T;
   const int r = blockIdx.x;
@@ -70,6 +69,39 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   int* box_prev = (int*)(ws + pick(L.box, prv));
   int* box_cur = (int*)(ws + pick(L.box, cur));
 
+  // ---- issue every global load up front.  The probe row r (slot 0), its
+  //      patch row and spectra and the max partials do not depend on the box
+  //      geometry, so they are issued before the positions are even read;
+  //      the rows that depend on the boxes follow.
+  float2 pv[3][MM];      // psi_prev rows (row-transformed spectra)
+  float2 Pq[3][MM];      // old probe at the slot rows
+  float2 oq[3];          // old patch at the slot rows
+  float2 og = make_float2(0.f, 0.f);  // object value of the next box row, outside the updated row
+  float2 Ph[MM];         // probe row r when there is no previous step
+  float om_in = 0.f, pm_in = 0.f, i_touch = 0.f;
+  const int c = tid;
+  if (lane) {
+    const size_t off = (size_t)r * N + c;
+    if (has_prev) {
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          pv[0][p] = psi_prev[p * NN + off];
+          Pq[0][p] = Pold[p * NN + off];
+        }
+      oq[0] = patch_prev[off];
+      om_in = ((const float*)(ws + pick(L.omax, prv)))[c];
+      pm_in = ((const float*)(ws + pick(L.pmax, prv)))[c];
+    } else {
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) Ph[p] = Pnew[p * NN + off];
+    }
+    // touch row r of this step's pattern so the column pass that follows
+    // finds it in the memory-side cache instead of HBM
+    if (has_next) i_touch = jb.I[(size_t)jn * NN + off];
+  }
+
   // ---- box geometry
   int ny_n = 0, nx_n = 0;
   if (has_next) {
@@ -93,18 +125,9 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   const bool u1 = rb1 >= 0 && rb1 != r, u2 = rb2 >= 0 && rb2 != r;
   const int rows[3] = {r, u1 ? rb1 : rb2, rb2};
   const int ns = has_prev ? 1 + (int)u1 + (int)u2 : 0;
-
-  // ---- issue every global load up front
-  float2 pv[3][MM];      // psi_prev rows (row-transformed spectra)
-  float2 Pq[3][MM];      // old probe at the slot rows
-  float2 oq[3];          // old patch at the slot rows
-  float2 og = make_float2(0.f, 0.f);  // object value of the next box row, outside the updated row
-  float2 Ph[MM];         // probe row r when there is no previous step
-  float om_in = 0.f, pm_in = 0.f;
-  const int c = tid;
   if (lane) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 1; q < 3; ++q) {
       if (q >= ns) break;
       const size_t off = (size_t)rows[q] * N + c;
 #pragma unroll
@@ -114,14 +137,6 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
           Pq[q][p] = Pold[p * NN + off];
         }
       oq[q] = patch_prev[off];
-    }
-    if (has_prev) {
-      om_in = ((const float*)(ws + pick(L.omax, prv)))[c];
-      pm_in = ((const float*)(ws + pick(L.pmax, prv)))[c];
-    } else {
-#pragma unroll
-      for (int p = 0; p < MM; ++p)
-        if (p < M) Ph[p] = Pnew[p * NN + (size_t)r * N + c];
     }
     if (has_next) {
       const int gx = nx_n + c;
@@ -243,11 +258,11 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     const int p = i / N, cc = i - p * N;
     dst[p * NN + (size_t)r * N + cc] = res[i];
   }
+  if (i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
 
-template <int N, bool R4>
+template <int N, bool R4, int MM>
 __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES;
   const int M = jb.M;
   const int total = jb.J * jb.T;
   if (t >= total) return;
@@ -314,30 +329,62 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   if (threadIdx.x == 0) *err_slot = err_old + e;
 }
 
-template <bool R4>
+// R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
+// (jobs of the launch have M <= MM), so small M does not pay the register
+// cost (and occupancy) of the largest.
+template <bool R4, int MM>
 __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
-    case 32: rows_body<32, R4>(a.c, jb, t, smem); break;
-    case 64: rows_body<64, R4>(a.c, jb, t, smem); break;
-    case 128: rows_body<128, R4>(a.c, jb, t, smem); break;
-    case 192: rows_body<192, R4>(a.c, jb, t, smem); break;
-    default: rows_body<256, R4>(a.c, jb, t, smem); break;
+    case 32: rows_body<32, R4, MM>(a.c, jb, t, smem); break;
+    case 64: rows_body<64, R4, MM>(a.c, jb, t, smem); break;
+    case 128: rows_body<128, R4, MM>(a.c, jb, t, smem); break;
+    case 192: rows_body<192, R4, MM>(a.c, jb, t, smem); break;
+    default: rows_body<256, R4, MM>(a.c, jb, t, smem); break;
   }
 }
 
-template <bool R4>
+template <bool R4, int MM>
 __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
-    case 32: cols_body<32, R4>(jb, t, smem); break;
-    case 64: cols_body<64, R4>(jb, t, smem); break;
-    case 128: cols_body<128, R4>(jb, t, smem); break;
-    case 192: cols_body<192, R4>(jb, t, smem); break;
-    default: cols_body<256, R4>(jb, t, smem); break;
+    case 32: cols_body<32, R4, MM>(jb, t, smem); break;
+    case 64: cols_body<64, R4, MM>(jb, t, smem); break;
+    case 128: cols_body<128, R4, MM>(jb, t, smem); break;
+    case 192: cols_body<192, R4, MM>(jb, t, smem); break;
+    default: cols_body<256, R4, MM>(jb, t, smem); break;
   }
+}
+
+using SweepKernel = void (*)(const LaunchArgs, int);
+
+static int mode_class(int M) { return M <= 1 ? 1 : M <= 2 ? 2 : M <= 4 ? 4 : 8; }
+
+template <bool R4>
+static SweepKernel pick_rows(int mc) {
+  switch (mc) {
+    case 1: return k_rows<R4, 1>;
+    case 2: return k_rows<R4, 2>;
+    case 4: return k_rows<R4, 4>;
+    default: return k_rows<R4, 8>;
+  }
+}
+template <bool R4>
+static SweepKernel pick_cols(int mc) {
+  switch (mc) {
+    case 1: return k_cols<R4, 1>;
+    case 2: return k_cols<R4, 2>;
+    case 4: return k_cols<R4, 4>;
+    default: return k_cols<R4, 8>;
+  }
+}
+static SweepKernel rows_kernel(int radix, int maxM) {
+  return radix == 8 ? pick_rows<false>(mode_class(maxM)) : pick_rows<true>(mode_class(maxM));
+}
+static SweepKernel cols_kernel(int radix, int maxM) {
+  return radix == 8 ? pick_cols<false>(mode_class(maxM)) : pick_cols<true>(mode_class(maxM));
 }
 
 // ------------------------------------------------------- small kernels
@@ -430,10 +477,11 @@ void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t 
   size_t lc = 0;
   for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M));
   const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
-  (void)ensure_lds(tu.cols_radix == 8 ? (const void*)k_cols<false> : (const void*)k_cols<true>, lc);
-  TimingScope ts(TK_COLS, s);
-  if (tu.cols_radix == 8) hipLaunchKernelGGL(k_cols<false>, dim3(maxN, nb), dim3(256), lc, s, a, t);
-  else hipLaunchKernelGGL(k_cols<true>, dim3(maxN, nb), dim3(256), lc, s, a, t);
+  int maxM = 1;
+  for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
+  const SweepKernel kc = cols_kernel(tu.cols_radix, maxM);
+  (void)ensure_lds((const void*)kc, lc);
+  launch_k(TK_COLS, kc, dim3(maxN, nb), dim3(256), lc, s, a, t);
 }
 
 void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
@@ -469,24 +517,18 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
       eo.p[b] = err_out ? err_out[c0 + b] : nullptr;
     }
     const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
-    const void* kr = tu.rows_radix == 8 ? (const void*)k_rows<false> : (const void*)k_rows<true>;
-    const void* kc = tu.cols_radix == 8 ? (const void*)k_cols<false> : (const void*)k_cols<true>;
-    MRPIE_HIP(ensure_lds(kr, lr));
-    MRPIE_HIP(ensure_lds(kc, lc));
+    int maxM = 1;
+    for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
+    const SweepKernel kr = rows_kernel(tu.rows_radix, maxM);
+    const SweepKernel kc = cols_kernel(tu.cols_radix, maxM);
+    MRPIE_HIP(ensure_lds((const void*)kr, lr));
+    MRPIE_HIP(ensure_lds((const void*)kc, lc));
     const dim3 blk(256), rblk(tu.rows_threads);
     hipLaunchKernelGGL(k_zero_err, dim3(8, nb), blk, 0, s, a);
     if (maxTot == 0) continue;
     for (int t = 0; t <= maxTot; ++t) {
-      {
-        TimingScope ts(TK_ROWS, s);
-        if (tu.rows_radix == 8) hipLaunchKernelGGL(k_rows<false>, dim3(maxN, nb), rblk, lr, s, a, t);
-        else hipLaunchKernelGGL(k_rows<true>, dim3(maxN, nb), rblk, lr, s, a, t);
-      }
-      if (t < maxTot) {
-        TimingScope ts(TK_COLS, s);
-        if (tu.cols_radix == 8) hipLaunchKernelGGL(k_cols<false>, dim3(maxN, nb), blk, lc, s, a, t);
-        else hipLaunchKernelGGL(k_cols<true>, dim3(maxN, nb), blk, lc, s, a, t);
-      }
+      launch_k(TK_ROWS, kr, dim3(maxN, nb), rblk, lr, s, a, t);
+      if (t < maxTot) launch_k(TK_COLS, kc, dim3(maxN, nb), blk, lc, s, a, t);
     }
     hipLaunchKernelGGL(k_probe_back, dim3(64, nb), blk, 0, s, a);
     hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), blk, 0, s, a);

@@ -383,10 +383,7 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
   const dim3 g(N), blk(256);
   const int t0 = it0 * jb.J, t1 = (it0 + iters) * jb.J;
   for (int t = t0; t < t1; ++t) {
-    {
-      TimingScope ts(TK_ROWS, s);
-      hipLaunchKernelGGL(k_sp_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
-    }
+    hipLaunchKernelGGL(k_sp_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
     hipLaunchKernelGGL(k_sp_ramp, g, blk, lr, s, a, t, 0);
     hipLaunchKernelGGL(k_sp_exit, g, blk, le, s, a, t);
     launch_cols_pass(a.la, N, 1, t, s);
