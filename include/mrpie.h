@@ -156,12 +156,17 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * than one job).  rows_radix / cols_radix: 4 or 8, the radix of the LDS
  * Stockham FFT stages of the row / column pass (radix 4: more threads per
  * transform, shorter latency; radix 8: fewer stages, less LDS traffic);
- * rows_threads: 256 or 512 threads per row workgroup.  The setting is
+ * rows_threads: 256 or 512 threads per row workgroup; lds_sweep in
+ * [0, 8]: a job with M <= lds_sweep whose modes fit the LDS together
+ * (M N^2 <= 16384: 32^2 with up to 8 modes, 64^2 with up to 4, 128^2 with
+ * 1) runs as one workgroup that keeps the probe in registers and the 2-D
+ * FFT in LDS for the whole call; other jobs run the row / column passes
+ * (default: 8 for N = 32, 1 for N = 64, 0 otherwise).  The setting is
  * process-wide host state; results do not depend on it beyond float
  * rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
  * candidates on the device and installs the fastest with mrpie_set_tuning. */
 typedef struct {
-  int32_t rows_radix, cols_radix, rows_threads;
+  int32_t rows_radix, cols_radix, rows_threads, lds_sweep;
 } mrpie_tuning;
 int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
 int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);

@@ -71,16 +71,49 @@ __device__ __forceinline__ void load_twiddles(double2* s_tw) {
   for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw64[idx][i];
 }
 
-// Workgroup reductions (64-wide waves).
+// Wave reductions (64-wide waves, every lane active).  DPP row shifts by
+// 1, 2, 4, 8 leave in lane 15 of each row of 16 the reduction of its row
+// (lanes shifted in from outside a row read 0, the identity of both
+// reductions below); the four row results are then combined in a fixed
+// order through scalar registers.  The result is uniform over the wave.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// max over the wave of NON-NEGATIVE values
 __device__ __forceinline__ float wave_max(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmaxf(v, dpp_f<0x111>(v));  // row_shr:1
+  v = fmaxf(v, dpp_f<0x112>(v));  // row_shr:2
+  v = fmaxf(v, dpp_f<0x114>(v));  // row_shr:4
+  v = fmaxf(v, dpp_f<0x118>(v));  // row_shr:8
+  return fmaxf(fmaxf(lane_f(v, 15), lane_f(v, 31)), fmaxf(lane_f(v, 47), lane_f(v, 63)));
 }
+// sum over the wave, in a fixed order (deterministic)
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0x111>(v);
+  v += dpp_d<0x112>(v);
+  v += dpp_d<0x114>(v);
+  v += dpp_d<0x118>(v);
+  return (lane_d(v, 15) + lane_d(v, 31)) + (lane_d(v, 47) + lane_d(v, 63));
 }
-// red: >= 16 floats of LDS.  All threads get the result.
+// Workgroup reductions.  red: >= 16 floats of LDS; v >= 0.  All threads
+// get the result.
 __device__ __forceinline__ float block_max(float v, float* red) {
   v = wave_max(v);
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -137,7 +170,7 @@ hipError_t ensure_lds(const void* kernel, size_t bytes);
 // launch of a timed kernel class is launched with hipExtLaunchKernelGGL and
 // a start / stop event pair, so the events carry that dispatch's own start
 // and end time on its stream; mrpie_timing_read() averages them.
-enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_COUNT = 8 };
+enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_LDS = 5, TK_COUNT = 8 };
 struct TimedLaunch {
   hipEvent_t start = nullptr, stop = nullptr;
 };

@@ -308,12 +308,14 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) S += cabs2(F[p * N + k]);
-    const float Au = sqrtf(S);
-    const float sq = sqrtf(fmaxf(Iv, 0.f));
+    // hardware reciprocal square root and square root (about 1 ulp)
+    const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+    const float Au = S * rs;
+    const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv, 0.f));
     const float d = Au * invN - sq;
     e = (double)d * (double)d;
     if (!isfinite(S)) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
-    const float f = S > 0.f ? sq / Au * invN : 0.f;
+    const float f = sq * rs * invN;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) G[p * N + k] = cscale(F[p * N + k], f);
@@ -447,8 +449,13 @@ __global__ void k_probe_back(const LaunchArgs a) {
 
 // ------------------------------------------------------------ tuning
 // Launch shapes of the sweep, per (N, batch class): FFT radix plan of each
-// pass and threads per row workgroup.  The default (radix 8 in both passes,
-// 256 threads) was the fastest measured for 256^2 x 3 on MI355X; the
+// pass, threads per row workgroup, and up to which mode count a job whose
+// modes fit the LDS runs the one-workgroup sweep.  The defaults were the
+// fastest measured on MI355X: radix 8 in both passes with 256 threads for
+// 256^2 x 3; the one-workgroup sweep for 32^2 (5 modes: 9.3 against 12.9 us
+// per position) and 64^2 x 1 (9.6 against 11.6 us), the passes from 64^2 x 3
+// (13.3 against 20.0 us) and 128^2 x 1 (12.3 against 42.3 us) on, where one
+// CU's vector ALUs and LDS bandwidth bound the one-workgroup sweep.  The
 // autotuner measures the alternatives on the device for any (N, M, batch).
 static Tuning g_tune[4][2];
 static bool g_tune_set[4][2];
@@ -459,7 +466,7 @@ Tuning get_tuning(int N, int M, int nb) {
   (void)M;
   const int ni = n_index(N), bc = batch_class(nb);
   if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
-  return Tuning{8, 8, 256};
+  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0};
 }
 
 void set_tuning(int N, int nb, const Tuning& t) {
@@ -488,15 +495,16 @@ void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_err, dim3(8, nb), dim3(256), 0, s, a);
 }
 
-void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s) {
+void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s, bool probe_back) {
   ErrOut eo{};
   for (int b = 0; b < nb; ++b) eo.p[b] = err_out ? err_out[b] : nullptr;
-  hipLaunchKernelGGL(k_probe_back, dim3(64, nb), dim3(256), 0, s, a);
+  if (probe_back) hipLaunchKernelGGL(k_probe_back, dim3(64, nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_finish, dim3(1, nb), dim3(256), 0, s, a, eo);
 }
 
-int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
+// Row / column passes, lock-step over the jobs.
+static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
   int rc = launch_init_twiddles(s);
   if (rc) return rc;
   for (int c0 = 0; c0 < njobs; c0 += kMaxJobsPerLaunch) {
@@ -535,6 +543,26 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
     hipLaunchKernelGGL(k_finish, dim3(1, nb), blk, 0, s, a, eo);
     MRPIE_HIP(hipGetLastError());
   }
+  return MRPIE_OK;
+}
+
+// Jobs whose modes fit the LDS (and whose tuning allows it) run the
+// one-workgroup sweep; the rest run the row / column passes.  Both groups
+// are issued on `s`, one after the other.
+int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
+  std::vector<JobRec> lj, pj;
+  std::vector<float*> le, pe;
+  for (int b = 0; b < njobs; ++b) {
+    const JobRec& jb = jobs[b];
+    const bool lds = jb.M <= get_tuning(jb.N, jb.M, njobs).lds_sweep && lds_sweep_fits(jb.N, jb.M);
+    (lds ? lj : pj).push_back(jb);
+    (lds ? le : pe).push_back(err_out ? err_out[b] : nullptr);
+  }
+  if (!lj.empty()) {
+    int rc = run_lds_sweep(c, lj.data(), (int)lj.size(), le.data(), s);
+    if (rc) return rc;
+  }
+  if (!pj.empty()) return run_passes(c, pj.data(), (int)pj.size(), pe.data(), s);
   return MRPIE_OK;
 }
 
@@ -672,7 +700,8 @@ int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
   if ((t->rows_radix != 4 && t->rows_radix != 8) || (t->cols_radix != 4 && t->cols_radix != 8))
     return fail(MRPIE_EINVAL, "radix must be 4 or 8");
   if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
-  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads});
+  if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
+  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep});
   return MRPIE_OK;
 }
 
@@ -683,6 +712,7 @@ int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
   t->rows_radix = u.rows_radix;
   t->cols_radix = u.cols_radix;
   t->rows_threads = u.rows_threads;
+  t->lds_sweep = u.lds_sweep;
   return MRPIE_OK;
 }
 

@@ -71,6 +71,8 @@ struct Tuning {
   int rows_radix;    // 4 or 8: FFT plan of the row pass
   int cols_radix;    // 4 or 8: FFT plan of the column pass
   int rows_threads;  // 256 or 512 threads per row workgroup
+  int lds_sweep;     // jobs with M <= lds_sweep whose modes fit the LDS run the
+                     // one-workgroup sweep (0: never)
 };
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);
@@ -89,6 +91,18 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
 size_t rpie_ws_total(const mrpie_problem* pb, const mrpie_params* pr);
 int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr, float* adam, float* err_out,
                        hipStream_t s);
+
+// Launch helpers shared by the sweep drivers: clear the per-iteration error
+// partials; finish (copy the probe back from the workspace buffer when
+// `probe_back`, sum the intensities, write err_out); one column pass.
+void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s);
+void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s, bool probe_back = true);
+void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s);
+
+// One-workgroup sweep of jobs whose M modes of N x N fit the LDS together
+// (M N^2 <= 16384); every job of `jobs` must fit.
+bool lds_sweep_fits(int N, int M);
+int run_lds_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s);
 
 // Host driver: runs `T` iterations (per job) of the sweep for every job in
 // `jobs` (any mix of N and M), lock-step by position: tick t performs the

@@ -357,9 +357,6 @@ __global__ __launch_bounds__(256) void k_sp_update(const SpArgs a, int t) {
 }
 
 // the modulus column pass of the integer-crop sweep (sweep.hip)
-void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s);
-void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s);
-void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s);
 
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s) {

@@ -1,5 +1,6 @@
 """Autotuner of the sweep's launch shapes (FFT radix plan per pass, threads
-per row workgroup).
+per row workgroup, and, for probes whose modes fit the LDS, the
+one-workgroup LDS sweep against the row / column passes).
 
 For a given probe size N, mode count M and batch size it runs a short
 synthetic sweep with every candidate shape through the C ABI, times it with
@@ -15,19 +16,27 @@ import torch
 
 from . import _abi, api
 
-CANDIDATES = [dict(rows_radix=rr, cols_radix=cr, rows_threads=th)
+CANDIDATES = [dict(rows_radix=rr, cols_radix=cr, rows_threads=th, lds_sweep=0)
               for rr, cr, th in itertools.product((4, 8), (4, 8), (256, 512))]
+LDS_CANDIDATE = dict(rows_radix=8, cols_radix=8, rows_threads=256, lds_sweep=8)
+_KEYS = ("rows_radix", "cols_radix", "rows_threads", "lds_sweep")
 
 
-def set_tuning(N, batched, rows_radix, cols_radix, rows_threads):
-    t = _abi.Tuning(rows_radix, cols_radix, rows_threads)
+def lds_fits(N, M):
+    """True when the M modes of an N x N probe fit the LDS together (the
+    one-workgroup sweep applies)."""
+    return N <= 128 and M * N * N <= 16384
+
+
+def set_tuning(N, batched, rows_radix, cols_radix, rows_threads, lds_sweep=0):
+    t = _abi.Tuning(rows_radix, cols_radix, rows_threads, lds_sweep)
     _abi.check(_abi.load().mrpie_set_tuning(N, int(bool(batched)), C.byref(t)))
 
 
 def get_tuning(N, batched):
     t = _abi.Tuning()
     _abi.check(_abi.load().mrpie_get_tuning(N, int(bool(batched)), C.byref(t)))
-    return dict(rows_radix=t.rows_radix, cols_radix=t.cols_radix, rows_threads=t.rows_threads)
+    return {k: getattr(t, k) for k in _KEYS}
 
 
 def _problem(N, M, J, dev, seed):
@@ -47,7 +56,8 @@ def autotune(N, M, batch=1, J=64, reps=3, device="cuda:0", verbose=False):
     jobs = [_problem(N, M, J, dev, 1234 + b) for b in range(batch)]
     batched = batch > 1
     times = {}
-    for cand in CANDIDATES:
+    cands = CANDIDATES + ([LDS_CANDIDATE] if lds_fits(N, M) else [])
+    for cand in cands:
         set_tuning(N, batched, **cand)
         best = float("inf")
         for _ in range(reps + 1):
@@ -66,6 +76,6 @@ def autotune(N, M, batch=1, J=64, reps=3, device="cuda:0", verbose=False):
         if verbose:
             print(cand, f"{best:.3f} ms")
     key = min(times, key=times.get)
-    best = dict(zip(("rows_radix", "cols_radix", "rows_threads"), key))
+    best = dict(zip(_KEYS, key))
     set_tuning(N, batched, **best)
     return best, times

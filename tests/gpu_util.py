@@ -1,5 +1,7 @@
 """Helpers for the GPU tests: move synthetic workloads to the device and run
 the HIP path through the C ABI."""
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -41,3 +43,15 @@ def run_gpu(w, prm, adam=None):
 
 def run_oracle(w, prm):
     return oracle.rpie64(w.O0, w.P0, w.pos0, w.I, oracle.Params(**prm))
+
+
+@contextlib.contextmanager
+def tuning(N, batched=False, **kw):
+    """Temporarily override fields of the launch tuning of (N, batched)."""
+    from paper_2205_04295_amd import tune
+    saved = tune.get_tuning(N, batched)
+    tune.set_tuning(N, batched, **dict(saved, **kw))
+    try:
+        yield
+    finally:
+        tune.set_tuning(N, batched, **saved)

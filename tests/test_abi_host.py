@@ -104,10 +104,17 @@ def test_register_and_adam_argument_checks(lib):
 
 
 def test_tuning_round_trip(lib):
-    t = _abi.Tuning(8, 4, 256)
+    d = _abi.Tuning()
+    assert lib.mrpie_get_tuning(128, 1, C.byref(d)) == 0
+    assert (d.rows_radix, d.cols_radix, d.rows_threads, d.lds_sweep) == (8, 8, 256, 0)
+    d64 = _abi.Tuning()
+    assert lib.mrpie_get_tuning(64, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
+    t = _abi.Tuning(8, 4, 256, 0)
     assert lib.mrpie_set_tuning(128, 1, C.byref(t)) == 0
     u = _abi.Tuning()
     assert lib.mrpie_get_tuning(128, 1, C.byref(u)) == 0
-    assert (u.rows_radix, u.cols_radix, u.rows_threads) == (8, 4, 256)
-    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(5, 4, 256))) == _abi.MRPIE_EINVAL
+    assert (u.rows_radix, u.cols_radix, u.rows_threads, u.lds_sweep) == (8, 4, 256, 0)
+    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(5, 4, 256, 1))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 9))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(100, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
+    assert lib.mrpie_set_tuning(128, 1, C.byref(d)) == 0  # restore the default

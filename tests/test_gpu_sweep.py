@@ -8,7 +8,7 @@ import torch
 import oracle
 from synth import workloads as wl
 
-from gpu_util import need_gpu, rel_l2, run_gpu, run_oracle
+from gpu_util import need_gpu, rel_l2, run_gpu, run_oracle, tuning
 
 pytestmark = pytest.mark.gpu
 
@@ -70,15 +70,53 @@ def test_sweep_one_iteration(name, bg):
     assert abs(g["err"][0] - o["err"][0]) <= 1e-4 * abs(o["err"][0])
 
 
-def test_raster_twenty_iterations():
+# probes whose modes fit the LDS together: the one-workgroup sweep (lds = 8)
+# and the row / column passes (lds = 0) must both match the oracle
+LDS_CASES = {
+    "n32m5": dict(seed=25, H=96, N=32, M=5, J=30),
+    "n64m1": dict(seed=21, H=192, N=64, M=1, J=40),
+    "n64m3": dict(seed=26, H=160, N=64, M=3, J=24),
+    "n128m1": dict(seed=27, H=320, N=128, M=1, J=16),
+}
+
+
+@pytest.mark.parametrize("name", list(LDS_CASES))
+@pytest.mark.parametrize("lds", [8, 0])
+def test_lds_sweep_and_passes_one_iteration(name, lds):
+    w = wl.small_case(name=name, **LDS_CASES[name])
+    prm = dict(w.params, iterations=1)
+    with tuning(w.P0.shape[-1], lds_sweep=lds):
+        g = run_gpu(w, prm)
+    o = run_oracle(w, prm)
+    assert g["status"] == 0
+    eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
+    print(f"{name} lds={lds}: rel L2 O {eo:.2e} P {ep:.2e}")
+    assert eo < 1e-4 and ep < 1e-4
+    assert abs(g["err"][0] - o["err"][0]) <= 1e-4 * abs(o["err"][0])
+
+
+def test_lds_sweep_is_bitwise_deterministic():
+    w = wl.small_case(name="n64m3", **LDS_CASES["n64m3"])
+    prm = dict(w.params, iterations=2)
+    with tuning(64, lds_sweep=8):
+        a = run_gpu(w, prm)
+        b = run_gpu(w, prm)
+    assert np.array_equal(a["O"], b["O"]) and np.array_equal(a["P"], b["P"])
+    assert np.array_equal(a["err"], b["err"])
+
+
+@pytest.mark.parametrize("lds", [8, 0])
+def test_raster_twenty_iterations(lds):
     """The 64^2 single-mode raster workload, 20 iterations, under the literal
-    reading of its parameters (M-ePIE, alpha_O = alpha_P = 0.1)."""
+    reading of its parameters (M-ePIE, alpha_O = alpha_P = 0.1), through the
+    one-workgroup LDS sweep and through the row / column passes."""
     w = wl.raster_case(seed=0)
     prm = dict(wl.R2_PARAMS, iterations=20)
-    g = run_gpu(w, prm)
+    with tuning(64, lds_sweep=lds):
+        g = run_gpu(w, prm)
     o = run_oracle(w, prm)
     eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
-    print(f"raster 20 it: rel L2 O {eo:.2e} P {ep:.2e}")
+    print(f"raster 20 it lds={lds}: rel L2 O {eo:.2e} P {ep:.2e}")
     assert eo < 1e-3 and ep < 1e-3
     assert np.allclose(g["err"], o["err"], rtol=1e-3)
     assert np.all(np.diff(g["err"]) <= 0)
@@ -198,6 +236,14 @@ def test_every_launch_shape_matches_oracle(name):
 
 def test_autotuner_installs_a_candidate():
     from paper_2205_04295_amd import tune
-    best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
-    assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
-    assert tune.get_tuning(64, False) == best
+    saved, saved256 = tune.get_tuning(64, False), tune.get_tuning(256, False)
+    try:
+        best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
+        cands = tune.CANDIDATES + [tune.LDS_CANDIDATE]
+        assert best in cands and len(times) == len(cands)
+        assert tune.get_tuning(64, False) == best
+        best, times = tune.autotune(256, 2, batch=1, J=4, reps=1)
+        assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
+    finally:
+        tune.set_tuning(64, False, **saved)
+        tune.set_tuning(256, False, **saved256)
