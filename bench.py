@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--uneven", type=float, default=0.25,
                     help="scan-length scale of the 64-job uneven batch (0 = skip, 1 = full)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep launch shapes first")
+    ap.add_argument("--small", type=int, default=1,
+                    help="also time the 64^2 raster workload (LDS sweep vs row / column passes)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -199,6 +201,40 @@ def measure_adjoint(api, torch, dev, obj, probe, pos, I, args):
             "loss": float(L.item())}
 
 
+def measure_small(api, torch, dev, args):
+    """The 64^2 single-mode raster workload (100 positions, 20 iterations per
+    run): the one-workgroup LDS sweep (default for this size) against the
+    row / column passes forced by the tuning."""
+    from paper_2205_04295_amd import tune
+    from synth import workloads as wl
+    w = wl.raster_case(seed=0)
+    N = w.P0.shape[-1]
+    J = w.pos0.shape[0]
+    T = 20
+    prm = dict(w.params)
+    prm["iterations"] = T
+    out = {"workload": "raster64x1: object 256^2, probe 64^2 x 1 mode, 10x10 raster, 20 iterations per run"}
+    saved = tune.get_tuning(N, False)
+    try:
+        for name, lds in (("lds_sweep", saved["lds_sweep"] or 8), ("passes", 0)):
+            tune.set_tuning(N, False, **dict(saved, lds_sweep=lds))
+            best = float("inf")
+            for r in range(4):
+                o, p = torch.from_numpy(w.O0).to(dev), torch.from_numpy(w.P0).to(dev)
+                pos, I = torch.from_numpy(w.pos0).to(dev), torch.from_numpy(w.I).to(dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                api.rpie(o, p, pos, I, **prm)
+                torch.cuda.synchronize()
+                if r:
+                    best = min(best, time.perf_counter() - t0)
+            out[name] = {"value": round(J * T / best, 1), "us_per_position": round(best * 1e6 / (J * T), 2)}
+    finally:
+        tune.set_tuning(N, False, **saved)
+    out["unit"] = "positions*iter/s"
+    return out
+
+
 def measure_uneven(api, torch, dev, args):
     """64 independent reconstructions of uneven N, M, J run in shared
     launches vs the same jobs run one after another through the plain sweep."""
@@ -318,6 +354,7 @@ def main():
     refine = measure_refine(api, torch, dev, args) if args.refine_iters > 0 else None
     adjoint = measure_adjoint(api, torch, dev, obj, probe, pos, I, args) if args.adjoint else None
     uneven = measure_uneven(api, torch, dev, args) if args.uneven > 0 else None
+    small = measure_small(api, torch, dev, args) if args.small else None
 
     if args.calib:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -363,6 +400,7 @@ def main():
         "refine": refine,
         "adjoint": adjoint,
         "uneven_batch": uneven,
+        "small_probe": small,
         "tuning": tuned,
         "cpu_baseline": cpu,
         "status": int(status.item()),

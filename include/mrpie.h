@@ -146,8 +146,10 @@ typedef struct {
  * refine and subpixel must be 0) on `njobs` independent reconstructions of
  * any mix of N, M, J and object size, lock-step by position: every launch
  * advances one position of every unfinished job, so one pair of launches
- * carries the work of all jobs.  Each job's result is bitwise equal to a
- * mrpie_rpie call on that job alone.  `jobs` is a HOST array read during
+ * carries the work of all jobs.  Each job's object and probe are bitwise
+ * equal to those of a mrpie_rpie call on that job alone when both use the
+ * same FFT radices (the defaults do); the error curve may differ in the
+ * summation order of its partial sums.  `jobs` is a HOST array read during
  * the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
 
@@ -161,12 +163,14 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * (M N^2 <= 16384: 32^2 with up to 8 modes, 64^2 with up to 4, 128^2 with
  * 1) runs as one workgroup that keeps the probe in registers and the 2-D
  * FFT in LDS for the whole call; other jobs run the row / column passes
- * (default: 8 for N = 32, 1 for N = 64, 0 otherwise).  The setting is
- * process-wide host state; results do not depend on it beyond float
- * rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
+ * (default: 8 for N = 32, 1 for N = 64, 0 otherwise); cols_width: 1 or 4
+ * adjacent detector columns per column-pass workgroup (1: shortest latency
+ * for a single sweep; 4: coalesced 32-byte row segments, for batches).  The
+ * setting is process-wide host state; results do not depend on it beyond
+ * float rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
  * candidates on the device and installs the fastest with mrpie_set_tuning. */
 typedef struct {
-  int32_t rows_radix, cols_radix, rows_threads, lds_sweep;
+  int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width;
 } mrpie_tuning;
 int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
 int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);

@@ -214,7 +214,7 @@ def validate(problem: Problem, **params) -> int:
     return lib.mrpie_validate(C.byref(problem), C.byref(prm))
 
 
-TIMED_KERNELS = ("k_rows", "k_cols", "k_reg_cols", "k_reg_gemm1", "k_adj_p4")
+TIMED_KERNELS = ("k_rows", "k_cols", "k_reg_cols", "k_reg_gemm1", "k_adj_p4", "k_lds_sweep")
 
 
 def timing_enable(stride: int):

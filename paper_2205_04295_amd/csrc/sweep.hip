@@ -261,74 +261,107 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   if (i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
 
-template <int N, bool R4, int MM>
+// Column pass of step t: CW adjacent detector columns per workgroup (all
+// modes), so that every global access of the pass moves CW * 8 contiguous
+// bytes of a row (CW = 1: a single column, the shortest latency; CW = 4:
+// a quarter of the cache-line traffic, for batches that fill the GPU).
+template <int N, bool R4, int MM, int CW>
 __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem) {
   const int M = jb.M;
   const int total = jb.J * jb.T;
   if (t >= total) return;
-  const int u = xcd_unit(blockIdx.x, gridDim.x);  // column of this workgroup
-  if (u >= N) return;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);  // column group of this workgroup
+  if (u >= N / CW) return;
+  const int u0 = u * CW;
   const int it = t / jb.J, jn = t - it * jb.J;
   const WsLayout L = ws_layout(N, M, jb.T);
   const size_t NN = (size_t)N * N;
   float2* psi = (float2*)(jb.ws + pick(L.psi, t & 1));
-  const int k = threadIdx.x;
-  const bool lane = k < N;
+  const float* Ij = jb.I + (size_t)jn * NN;
+  constexpr int NT = 256;               // threads
+  constexpr int PIX = (N * CW + NT - 1) / NT;  // detector pixels per thread
+  const int tid = threadIdx.x;
 
   float2* tw = smem;
-  float2* bufA = tw + N;
-  float2* bufB = bufA + M * N;
+  float2* bufA = tw + N;                // transform (p, c) at (p * CW + c) * N
+  float2* bufB = bufA + M * CW * N;
   __shared__ double redd[16];
 
   double* err_slot = (double*)(jb.ws + L.err) + (size_t)it * kErrSlots + u;
-  const double err_old = threadIdx.x == 0 ? *err_slot : 0.0;
-  float Iv = 0.f;
-  float2 v[MM];
-  if (lane) {
-    Iv = jb.I[(size_t)jn * NN + (size_t)k * N + u];
+  const double err_old = tid == 0 ? *err_slot : 0.0;
+  // pixel q = tid + NT * i of the group: row k = q / CW, column c = q % CW
+  // (consecutive threads read consecutive columns of a row)
+  float Iv[PIX];
+  float2 v[PIX][MM];
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) v[p] = psi[p * NN + (size_t)k * N + u];
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + NT * i;
+    if (q < N * CW) {
+      const int k = q / CW, c = q - k * CW;
+      const size_t off = (size_t)k * N + u0 + c;
+      Iv[i] = Ij[off];
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) v[i][p] = psi[p * NN + off];
+    }
   }
   load_twiddles<N>(tw);
-  if (lane) {
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) bufA[p * N + k] = v[p];
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + NT * i;
+    if (q < N * CW) {
+      const int k = q / CW, c = q - k * CW;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) bufA[(p * CW + c) * N + k] = v[i][p];
+    }
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, R4>(bufA, bufB, M, tw);
+  float2* F = fft_lds<N, false, R4>(bufA, bufB, M * CW, tw);
   float2* G = (F == bufA) ? bufB : bufA;
   // Eq. 7: the 2-D transform here is unnormalised (N x unitary) and so is
   // the inverse, so the scale factor carries one 1/N.
   const float invN = 1.0f / (float)N;
   double e = 0.0;
-  if (lane) {
-    float S = 0.f;
+  bool bad = false;
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) S += cabs2(F[p * N + k]);
-    // hardware reciprocal square root and square root (about 1 ulp)
-    const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
-    const float Au = S * rs;
-    const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv, 0.f));
-    const float d = Au * invN - sq;
-    e = (double)d * (double)d;
-    if (!isfinite(S)) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
-    const float f = sq * rs * invN;
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + NT * i;
+    if (q < N * CW) {
+      const int k = q / CW, c = q - k * CW;
+      float S = 0.f;
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) G[p * N + k] = cscale(F[p * N + k], f);
+      for (int p = 0; p < MM; ++p)
+        if (p < M) S += cabs2(F[(p * CW + c) * N + k]);
+      // hardware reciprocal square root and square root (about 1 ulp)
+      const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+      const float Au = S * rs;
+      const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv[i], 0.f));
+      const float d = Au * invN - sq;
+      e += (double)d * (double)d;
+      bad |= !isfinite(S);
+      const float f = sq * rs * invN;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) G[(p * CW + c) * N + k] = cscale(F[(p * CW + c) * N + k], f);
+    }
   }
+  if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
   __syncthreads();
-  float2* H = fft_lds<N, true, R4>(G, F, M, tw);
-  if (lane) {
+  float2* H = fft_lds<N, true, R4>(G, F, M * CW, tw);
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + (size_t)k * N + u] = H[p * N + k];
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + NT * i;
+    if (q < N * CW) {
+      const int k = q / CW, c = q - k * CW;
+      const size_t off = (size_t)k * N + u0 + c;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) psi[p * NN + off] = H[(p * CW + c) * N + k];
+    }
   }
   e = block_sum(e, redd);
-  if (threadIdx.x == 0) *err_slot = err_old + e;
+  if (tid == 0) *err_slot = err_old + e;
 }
 
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
@@ -347,16 +380,16 @@ __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
   }
 }
 
-template <bool R4, int MM>
+template <bool R4, int MM, int CW>
 __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
-    case 32: cols_body<32, R4, MM>(jb, t, smem); break;
-    case 64: cols_body<64, R4, MM>(jb, t, smem); break;
-    case 128: cols_body<128, R4, MM>(jb, t, smem); break;
-    case 192: cols_body<192, R4, MM>(jb, t, smem); break;
-    default: cols_body<256, R4, MM>(jb, t, smem); break;
+    case 32: cols_body<32, R4, MM, CW>(jb, t, smem); break;
+    case 64: cols_body<64, R4, MM, CW>(jb, t, smem); break;
+    case 128: cols_body<128, R4, MM, CW>(jb, t, smem); break;
+    case 192: cols_body<192, R4, MM, CW>(jb, t, smem); break;
+    default: cols_body<256, R4, MM, CW>(jb, t, smem); break;
   }
 }
 
@@ -373,20 +406,22 @@ static SweepKernel pick_rows(int mc) {
     default: return k_rows<R4, 8>;
   }
 }
-template <bool R4>
+template <bool R4, int CW>
 static SweepKernel pick_cols(int mc) {
   switch (mc) {
-    case 1: return k_cols<R4, 1>;
-    case 2: return k_cols<R4, 2>;
-    case 4: return k_cols<R4, 4>;
-    default: return k_cols<R4, 8>;
+    case 1: return k_cols<R4, 1, CW>;
+    case 2: return k_cols<R4, 2, CW>;
+    case 4: return k_cols<R4, 4, CW>;
+    default: return k_cols<R4, 8, CW>;
   }
 }
 static SweepKernel rows_kernel(int radix, int maxM) {
   return radix == 8 ? pick_rows<false>(mode_class(maxM)) : pick_rows<true>(mode_class(maxM));
 }
-static SweepKernel cols_kernel(int radix, int maxM) {
-  return radix == 8 ? pick_cols<false>(mode_class(maxM)) : pick_cols<true>(mode_class(maxM));
+static SweepKernel cols_kernel(int radix, int width, int maxM) {
+  const int mc = mode_class(maxM);
+  if (width == 4) return radix == 8 ? pick_cols<false, 4>(mc) : pick_cols<true, 4>(mc);
+  return radix == 8 ? pick_cols<false, 1>(mc) : pick_cols<true, 1>(mc);
 }
 
 // ------------------------------------------------------- small kernels
@@ -455,7 +490,10 @@ __global__ void k_probe_back(const LaunchArgs a) {
 // 256^2 x 3; the one-workgroup sweep for 32^2 (5 modes: 9.3 against 12.9 us
 // per position) and 64^2 x 1 (9.6 against 11.6 us), the passes from 64^2 x 3
 // (13.3 against 20.0 us) and 128^2 x 1 (12.3 against 42.3 us) on, where one
-// CU's vector ALUs and LDS bandwidth bound the one-workgroup sweep.  The
+// CU's vector ALUs and LDS bandwidth bound the one-workgroup sweep; one
+// detector column per column workgroup for a single sweep (19.5 against
+// 23.3 us per position at 256^2 x 3), four in batches (8 jobs: 52.1 against
+// 57.2 us per lock-step position, 32 jobs: 168 against 182 us).  The
 // autotuner measures the alternatives on the device for any (N, M, batch).
 static Tuning g_tune[4][2];
 static bool g_tune_set[4][2];
@@ -466,7 +504,7 @@ Tuning get_tuning(int N, int M, int nb) {
   (void)M;
   const int ni = n_index(N), bc = batch_class(nb);
   if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
-  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0};
+  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1};
 }
 
 void set_tuning(int N, int nb, const Tuning& t) {
@@ -478,17 +516,17 @@ void set_tuning(int N, int nb, const Tuning& t) {
 
 // ------------------------------------------------------------ host driver
 static size_t rows_lds(int N, int M) { return (size_t)(N + N + 6 * M * N) * 8; }
-static size_t cols_lds(int N, int M) { return (size_t)(N + 2 * M * N) * 8; }
+static size_t cols_lds(int N, int M, int cw) { return (size_t)(N + 2 * cw * M * N) * 8; }
 
 void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s) {
-  size_t lc = 0;
-  for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M));
   const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+  size_t lc = 0;
+  for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M, tu.cols_width));
   int maxM = 1;
   for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
-  const SweepKernel kc = cols_kernel(tu.cols_radix, maxM);
+  const SweepKernel kc = cols_kernel(tu.cols_radix, tu.cols_width, maxM);
   (void)ensure_lds((const void*)kc, lc);
-  launch_k(TK_COLS, kc, dim3(maxN, nb), dim3(256), lc, s, a, t);
+  launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), dim3(256), lc, s, a, t);
 }
 
 void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
@@ -521,14 +559,14 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
       maxN = std::max(maxN, jb.N);
       maxTot = std::max(maxTot, jb.J * jb.T);
       lr = std::max(lr, rows_lds(jb.N, jb.M));
-      lc = std::max(lc, cols_lds(jb.N, jb.M));
       eo.p[b] = err_out ? err_out[c0 + b] : nullptr;
     }
     const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+    for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M, tu.cols_width));
     int maxM = 1;
     for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
     const SweepKernel kr = rows_kernel(tu.rows_radix, maxM);
-    const SweepKernel kc = cols_kernel(tu.cols_radix, maxM);
+    const SweepKernel kc = cols_kernel(tu.cols_radix, tu.cols_width, maxM);
     MRPIE_HIP(ensure_lds((const void*)kr, lr));
     MRPIE_HIP(ensure_lds((const void*)kc, lc));
     const dim3 blk(256), rblk(tu.rows_threads);
@@ -536,7 +574,7 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
     if (maxTot == 0) continue;
     for (int t = 0; t <= maxTot; ++t) {
       launch_k(TK_ROWS, kr, dim3(maxN, nb), rblk, lr, s, a, t);
-      if (t < maxTot) launch_k(TK_COLS, kc, dim3(maxN, nb), blk, lc, s, a, t);
+      if (t < maxTot) launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), blk, lc, s, a, t);
     }
     hipLaunchKernelGGL(k_probe_back, dim3(64, nb), blk, 0, s, a);
     hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), blk, 0, s, a);
@@ -701,7 +739,8 @@ int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
     return fail(MRPIE_EINVAL, "radix must be 4 or 8");
   if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
   if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
-  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep});
+  if (t->cols_width != 1 && t->cols_width != 4) return fail(MRPIE_EINVAL, "cols_width must be 1 or 4");
+  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width});
   return MRPIE_OK;
 }
 
@@ -713,6 +752,7 @@ int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
   t->cols_radix = u.cols_radix;
   t->rows_threads = u.rows_threads;
   t->lds_sweep = u.lds_sweep;
+  t->cols_width = u.cols_width;
   return MRPIE_OK;
 }
 

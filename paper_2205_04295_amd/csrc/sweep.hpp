@@ -73,6 +73,7 @@ struct Tuning {
   int rows_threads;  // 256 or 512 threads per row workgroup
   int lds_sweep;     // jobs with M <= lds_sweep whose modes fit the LDS run the
                      // one-workgroup sweep (0: never)
+  int cols_width;    // 1 or 4 adjacent detector columns per column workgroup
 };
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);
