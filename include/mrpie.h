@@ -79,7 +79,10 @@ typedef struct {
  *          updated o'_j, Adam step per position, Eq. 8-9 and Alg. 1) in
  *          iterations >= refine_start
  *  upsample : registration upsampling factor (window ceil(1.5 up) samples)
- *  xcorr_norm: 0 = plain cross-power spectrum, 1 = phase-normalised
+ *  xcorr_norm: 0 = plain cross-power spectrum (the reading used for
+ *          refinement: the paper follows the SciPy-ecosystem implementation
+ *          of Guizar-Sicairos et al., which does not normalise), 1 =
+ *          phase-normalised
  *  adam_lr, adam_b1, adam_b2, adam_eps : Adam hyper-parameters          */
 typedef struct {
   float alpha_obj, alpha_probe, beta, gamma;

@@ -32,8 +32,10 @@ listed in the design notes):
           band-limited Fourier shift o(r) = c(r + f) and the object update is
           shifted back by -f.  With it off, f is ignored.
   R-reg   Registration (Methods, "Adam-based position refinement", after
-          Guizar-Sicairos et al. 2008): X = F(ref) conj(F(mov)), optionally
-          phase-normalised; integer peak of |F^-1 X| (first maximum in
+          Guizar-Sicairos et al. 2008, whose SciPy-ecosystem implementation
+          the paper follows): X = F(ref) conj(F(mov)), unnormalised by
+          default as in that implementation, optionally phase-normalised;
+          integer peak of |F^-1 X| (first maximum in
           row-major order, lags above N//2 wrap negative); then a
           matrix-product DFT on a window of U = ceil(1.5 up) samples per axis
           at spacing 1/up centred (index floor(U/2)) on the integer peak.
@@ -80,7 +82,7 @@ class Params:
     refine: int = 0               # XCORR_A position refinement on/off
     refine_start: int = 0
     upsample: int = 100
-    xcorr_norm: int = 1           # 0 = plain cross-power, 1 = phase-normalised
+    xcorr_norm: int = 0           # 0 = plain cross-power (default), 1 = phase-normalised
     adam_lr: float = 0.5
     adam_b1: float = 0.9
     adam_b2: float = 0.999
@@ -219,7 +221,7 @@ def upsampled_window(X, s0, up):
     return Ky @ X @ Kx, c
 
 
-def register64(ref, mov, up=100, norm=1):
+def register64(ref, mov, up=100, norm=0):
     """Subpixel registration (Methods, position refinement; reading R-reg).
 
     Returns (shift[2], peak[4]) where shift = s0 + ((u*, v*) - c)/up and

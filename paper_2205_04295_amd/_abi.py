@@ -36,7 +36,7 @@ class Params(C.Structure):
 
 PARAM_DEFAULTS = dict(alpha_obj=1.0, alpha_probe=1.0, beta=1.0, gamma=1.0, iterations=1, iter_offset=0,
                       probe_update_start=0, subpixel=0, refine=0, refine_start=0, upsample=100,
-                      xcorr_norm=1, adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
+                      xcorr_norm=0, adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
 
 
 def make_params(**kw) -> Params:

@@ -96,7 +96,7 @@ def rpie_batched(jobs, stream=None, **params):
     return keep
 
 
-def register(ref, mov, upsample=100, norm=1, workspace=None, stream=None):
+def register(ref, mov, upsample=100, norm=0, workspace=None, stream=None):
     """Subpixel registration of pairs ref[b], mov[b] ([B, N, N] complex64).
     Returns (shift [B, 2] float32, peak [B, 4] int32) on the GPU."""
     lib = _abi.load()

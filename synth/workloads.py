@@ -208,7 +208,7 @@ def spiral_case(seed=1, H=1024, N=256, M=3, J=1600, R=32.0, c=9.6, photons=1e7,
     I, scale = simulate_patterns(rng, O, P, true, photons, noise)
     prm = dict(R1_PARAMS, iterations=iterations)
     if pos_sigma > 0:
-        prm.update(subpixel=1, refine=1, refine_start=0, upsample=100, xcorr_norm=1,
+        prm.update(subpixel=1, refine=1, refine_start=0, upsample=100, xcorr_norm=0,
                    adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
     return _finish(name, O, P, true, nominal, I, scale, R, prm, seed=seed)
 

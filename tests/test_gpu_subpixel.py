@@ -55,8 +55,8 @@ def test_subpixel_multi_iteration():
     assert rel_l2(g["O"], o["O"]) < 1e-3 and rel_l2(g["P"], o["P"]) < 1e-3
 
 
-@pytest.mark.parametrize("subpixel", [1, 0])
-def test_refinement_one_iteration(subpixel):
+@pytest.mark.parametrize("subpixel,norm", [(1, 0), (0, 0), (1, 1)])
+def test_refinement_one_iteration(subpixel, norm):
     """One refining iteration: the sweep itself matches the oracle; the
     measured shifts (recovered from Adam's first moment, m = (1-b1) g at
     t = 1) agree with the oracle's to the window spacing; where the shifts
@@ -67,7 +67,7 @@ def test_refinement_one_iteration(subpixel):
     w.pos0 = (w.pos_true + np.random.default_rng(3).normal(0, 2.0, size=w.pos_true.shape)).astype(np.float32)
     w.pos0 = np.clip(w.pos0, 0, 384 - 128).astype(np.float32)
     up = 1000
-    prm = dict(w.params, iterations=1, subpixel=subpixel, refine=1, upsample=up, xcorr_norm=1,
+    prm = dict(w.params, iterations=1, subpixel=subpixel, refine=1, upsample=up, xcorr_norm=norm,
                adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
     adam0 = np.zeros((w.pos0.shape[0], 4), np.float32)
     g = run_gpu(w, prm, adam=adam0)
