@@ -124,6 +124,25 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   for (int i = 1; i < nw; ++i) r = fmaxf(r, red[i]);
   return r;
 }
+// max of two values over the workgroup with one pair of barriers.  red: >= 32
+// floats of LDS; a, b >= 0.
+__device__ __forceinline__ void block_max2(float a, float b, float* red, float& ra, float& rb) {
+  a = wave_max(a);
+  b = wave_max(b);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[16 + w] = b;
+  }
+  __syncthreads();
+  ra = red[0];
+  rb = red[16];
+  for (int i = 1; i < nw; ++i) {
+    ra = fmaxf(ra, red[i]);
+    rb = fmaxf(rb, red[16 + i]);
+  }
+}
 // red: >= 16 doubles of LDS; fixed summation order (deterministic).
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);

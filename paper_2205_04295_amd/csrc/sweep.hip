@@ -60,7 +60,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
   float2* bufA = orow + N;         // 3*M*N
   float2* bufB = bufA + 3 * M * N; // 3*M*N
-  __shared__ float redf[16];
+  __shared__ float redf[32];
 
   const float2* psi_prev = (const float2*)(ws + pick(L.psi, prv));
   const float2* patch_prev = (const float2*)(ws + pick(L.patch, prv));
@@ -152,6 +152,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
 
   float2 Pn[MM];
   bool bad = false;
+  float pm_row = 0.f;  // sum_p |P_p|^2 of the new probe at (r, c)
   if (has_prev) {
     if (lane) {
 #pragma unroll
@@ -162,14 +163,13 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
           if (p < M) bufA[(q * M + p) * N + c] = pv[q][p];
       }
     }
-    const float omax = block_max(om_in, redf);
-    const float pmaxv = block_max(pm_in, redf + 8);  // (contains the barrier before the FFT)
+    float omax, pmaxv;
+    block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
     float2* res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
 
     // ---- probe update of row r (Eq. 5) from the pre-update o and P
     const int it_abs = cm.iter_offset + (t - 1) / jb.J;
     const bool upd_p = it_abs >= cm.probe_update_start;
-    float pm = 0.f;
     if (lane) {
       const float2 o = oq[0];
       const float o2 = cabs2(o);
@@ -186,10 +186,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
           ps += cabs2(Pn[p]);
         }
       bad |= !isfinite(ps);
-      pm = ps;
     }
-    pm = block_max(pm, redf);
-    if (tid == 0) ((float*)(ws + pick(L.pmax, cur)))[r] = pm;
 
     // ---- object update (Eq. 6) of box rows rb1 / rb2: slot 0 when one of
     //      them is the probe row r, slots 1.. otherwise
@@ -230,7 +227,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
 
   // ---- gather row r of the next box (merging the row just updated),
   //      exit waves and forward row FFTs
-  float om = 0.f, pm0 = 0.f;
+  float om = 0.f;
   if (lane) {
     const int gx = nx_n + c;
     const float2 o = (rb1 >= 0 && gx >= nx_p && gx < nx_p + N) ? orow[gx - nx_p] : og;
@@ -243,15 +240,14 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
         ps += cabs2(Pn[p]);
         bufA[p * N + c] = cmul(Pn[p], o);
       }
-    pm0 = ps;
+    pm_row = ps;
   }
-  om = block_max(om, redf);
-  if (!has_prev) pm0 = block_max(pm0, redf + 8);
+  float pm;
+  block_max2(om, pm_row, redf, om, pm);  // (its barriers also publish bufA)
   if (tid == 0) {
     ((float*)(ws + pick(L.omax, cur)))[r] = om;
-    if (!has_prev) ((float*)(ws + pick(L.pmax, cur)))[r] = pm0;
+    ((float*)(ws + pick(L.pmax, cur)))[r] = pm;
   }
-  __syncthreads();
   float2* res = fft_lds<N, false, R4>(bufA, bufB, M, tw);
   float2* dst = (float2*)(ws + pick(L.psi, cur));
   for (int i = tid; i < M * N; i += blockDim.x) {
@@ -285,10 +281,9 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   float2* tw = smem;
   float2* bufA = tw + N;                // transform (p, c) at (p * CW + c) * N
   float2* bufB = bufA + M * CW * N;
-  __shared__ double redd[16];
-
-  double* err_slot = (double*)(jb.ws + L.err) + (size_t)it * kErrSlots + u;
-  const double err_old = tid == 0 ? *err_slot : 0.0;
+  // per-wave partial of the Fourier error (kErrSlots / 256 waves per unit)
+  double* err_slot = (double*)(jb.ws + L.err) + (size_t)it * kErrSlots + u * (NT / 64) + (tid >> 6);
+  const double err_old = (tid & 63) == 0 ? *err_slot : 0.0;
   // pixel q = tid + NT * i of the group: row k = q / CW, column c = q % CW
   // (consecutive threads read consecutive columns of a row)
   float Iv[PIX];
@@ -360,8 +355,8 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
         if (p < M) psi[p * NN + off] = H[(p * CW + c) * N + k];
     }
   }
-  e = block_sum(e, redd);
-  if (tid == 0) *err_slot = err_old + e;
+  e = wave_sum(e);
+  if ((tid & 63) == 0) *err_slot = err_old + e;
 }
 
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
@@ -393,7 +388,41 @@ __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   }
 }
 
+// Single-job launches take the job as leading scalar arguments (NM = N |
+// M << 16), which gfx950 preloads into SGPRs: the first loads of a launch
+// do not wait for a kernel-argument fetch (about 1 us per launch).
+template <bool R4, int MM>
+__global__ __launch_bounds__(512) void k_rows1(char* ws, float2* obj, float2* probe, const float* pos, int t, int J,
+                                               int T, int NM, int H, int W, const float* I, int* status,
+                                               const Common c) {
+  extern __shared__ float2 smem[];
+  const JobRec jb{obj, probe, pos, I, ws, status, H, W, NM & 0xffff, NM >> 16, J, T};
+  switch (jb.N) {
+    case 32: rows_body<32, R4, MM>(c, jb, t, smem); break;
+    case 64: rows_body<64, R4, MM>(c, jb, t, smem); break;
+    case 128: rows_body<128, R4, MM>(c, jb, t, smem); break;
+    case 192: rows_body<192, R4, MM>(c, jb, t, smem); break;
+    default: rows_body<256, R4, MM>(c, jb, t, smem); break;
+  }
+}
+
+template <bool R4, int MM, int CW>
+__global__ __launch_bounds__(256) void k_cols1(char* ws, const float* I, int t, int J, int T, int NM, int* status) {
+  extern __shared__ float2 smem[];
+  const JobRec jb{nullptr, nullptr, nullptr, I, ws, status, 0, 0, NM & 0xffff, NM >> 16, J, T};
+  switch (jb.N) {
+    case 32: cols_body<32, R4, MM, CW>(jb, t, smem); break;
+    case 64: cols_body<64, R4, MM, CW>(jb, t, smem); break;
+    case 128: cols_body<128, R4, MM, CW>(jb, t, smem); break;
+    case 192: cols_body<192, R4, MM, CW>(jb, t, smem); break;
+    default: cols_body<256, R4, MM, CW>(jb, t, smem); break;
+  }
+}
+
 using SweepKernel = void (*)(const LaunchArgs, int);
+using RowsKernel1 = void (*)(char*, float2*, float2*, const float*, int, int, int, int, int, int, const float*, int*,
+                             const Common);
+using ColsKernel1 = void (*)(char*, const float*, int, int, int, int, int*);
 
 static int mode_class(int M) { return M <= 1 ? 1 : M <= 2 ? 2 : M <= 4 ? 4 : 8; }
 
@@ -414,6 +443,32 @@ static SweepKernel pick_cols(int mc) {
     case 4: return k_cols<R4, 4, CW>;
     default: return k_cols<R4, 8, CW>;
   }
+}
+template <bool R4>
+static RowsKernel1 pick_rows1(int mc) {
+  switch (mc) {
+    case 1: return k_rows1<R4, 1>;
+    case 2: return k_rows1<R4, 2>;
+    case 4: return k_rows1<R4, 4>;
+    default: return k_rows1<R4, 8>;
+  }
+}
+template <bool R4, int CW>
+static ColsKernel1 pick_cols1(int mc) {
+  switch (mc) {
+    case 1: return k_cols1<R4, 1, CW>;
+    case 2: return k_cols1<R4, 2, CW>;
+    case 4: return k_cols1<R4, 4, CW>;
+    default: return k_cols1<R4, 8, CW>;
+  }
+}
+static RowsKernel1 rows_kernel1(int radix, int M) {
+  return radix == 8 ? pick_rows1<false>(mode_class(M)) : pick_rows1<true>(mode_class(M));
+}
+static ColsKernel1 cols_kernel1(int radix, int width, int M) {
+  const int mc = mode_class(M);
+  if (width == 4) return radix == 8 ? pick_cols1<false, 4>(mc) : pick_cols1<true, 4>(mc);
+  return radix == 8 ? pick_cols1<false, 1>(mc) : pick_cols1<true, 1>(mc);
 }
 static SweepKernel rows_kernel(int radix, int maxM) {
   return radix == 8 ? pick_rows<false>(mode_class(maxM)) : pick_rows<true>(mode_class(maxM));
@@ -524,6 +579,14 @@ void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t 
   for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M, tu.cols_width));
   int maxM = 1;
   for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
+  if (nb == 1) {
+    const JobRec& jb = a.job[0];
+    const ColsKernel1 kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, jb.M);
+    (void)ensure_lds((const void*)kc1, lc);
+    launch_k(TK_COLS, kc1, dim3(maxN / tu.cols_width, 1), dim3(256), lc, s, jb.ws, jb.I, t, jb.J, jb.T,
+             jb.N | (jb.M << 16), jb.status);
+    return;
+  }
   const SweepKernel kc = cols_kernel(tu.cols_radix, tu.cols_width, maxM);
   (void)ensure_lds((const void*)kc, lc);
   launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), dim3(256), lc, s, a, t);
@@ -572,9 +635,24 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
     const dim3 blk(256), rblk(tu.rows_threads);
     hipLaunchKernelGGL(k_zero_err, dim3(8, nb), blk, 0, s, a);
     if (maxTot == 0) continue;
-    for (int t = 0; t <= maxTot; ++t) {
-      launch_k(TK_ROWS, kr, dim3(maxN, nb), rblk, lr, s, a, t);
-      if (t < maxTot) launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), blk, lc, s, a, t);
+    if (nb == 1) {
+      const JobRec& jb = a.job[0];
+      const RowsKernel1 kr1 = rows_kernel1(tu.rows_radix, jb.M);
+      const ColsKernel1 kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, jb.M);
+      MRPIE_HIP(ensure_lds((const void*)kr1, lr));
+      MRPIE_HIP(ensure_lds((const void*)kc1, lc));
+      const int NM = jb.N | (jb.M << 16);
+      for (int t = 0; t <= maxTot; ++t) {
+        launch_k(TK_ROWS, kr1, dim3(maxN, 1), rblk, lr, s, jb.ws, jb.obj, jb.probe, jb.pos, t, jb.J, jb.T, NM, jb.H,
+                 jb.W, jb.I, jb.status, c);
+        if (t < maxTot)
+          launch_k(TK_COLS, kc1, dim3(maxN / tu.cols_width, 1), blk, lc, s, jb.ws, jb.I, t, jb.J, jb.T, NM, jb.status);
+      }
+    } else {
+      for (int t = 0; t <= maxTot; ++t) {
+        launch_k(TK_ROWS, kr, dim3(maxN, nb), rblk, lr, s, a, t);
+        if (t < maxTot) launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), blk, lc, s, a, t);
+      }
     }
     hipLaunchKernelGGL(k_probe_back, dim3(64, nb), blk, 0, s, a);
     hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), blk, 0, s, a);

@@ -5,7 +5,7 @@
 
 namespace mrpie {
 
-constexpr int kErrSlots = 256;   // per-iteration error partials (one per column unit)
+constexpr int kErrSlots = 1024;  // per-iteration error partials (one per wave of each column unit)
 constexpr int kIsumParts = 256;  // partial sums of the intensities
 constexpr int kMaxJobsPerLaunch = 36;
 

@@ -142,25 +142,6 @@ __device__ __forceinline__ float2* lds_fft2(float2* a, float2* b, int M, const f
   return cur;
 }
 
-// max of two values over the workgroup (one pair of barriers)
-__device__ __forceinline__ void block_max2(float a, float b, float* red, float& ra, float& rb) {
-  a = wave_max(a);
-  b = wave_max(b);
-  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[w] = a;
-    red[16 + w] = b;
-  }
-  __syncthreads();
-  ra = red[0];
-  rb = red[16];
-  for (int i = 1; i < nw; ++i) {
-    ra = fmaxf(ra, red[i]);
-    rb = fmaxf(rb, red[16 + i]);
-  }
-}
-
 template <int N, int MM>
 __device__ __forceinline__ void lds_sweep_body(const Common& cm, const JobRec& jb, float2* smem, float* red,
                                                double* redd) {
