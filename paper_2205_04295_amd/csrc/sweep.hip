@@ -66,8 +66,6 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   const float2* patch_prev = (const float2*)(ws + pick(L.patch, prv));
   const float2* Pold = prv == 0 ? jb.probe : (const float2*)(ws + L.probe1);
   float2* Pnew = cur == 0 ? jb.probe : (float2*)(ws + L.probe1);
-  int* box_prev = (int*)(ws + pick(L.box, prv));
-  int* box_cur = (int*)(ws + pick(L.box, cur));
 
   // ---- issue every global load up front.  The probe row r (slot 0), its
   //      patch row and spectra and the max partials do not depend on the box
@@ -110,8 +108,12 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   }
   int ny_p = 0, nx_p = 0, rb1 = -1, rb2 = -1;
   if (has_prev) {
-    ny_p = box_prev[0];
-    nx_p = box_prev[1];
+    // the previous box, recomputed from the (read-only) positions: no wait
+    // for a value another XCD wrote one launch earlier (its clamp bit was
+    // set when it was gathered)
+    const int jp = (t - 1) % jb.J;
+    ny_p = box_corner(jb.pos[2 * jp], jb.H - N, nullptr);
+    nx_p = box_corner(jb.pos[2 * jp + 1], jb.W - N, nullptr);
     if (has_next) {
       const int dy = ny_n - ny_p;
       if (r + dy >= 0 && r + dy < N) rb1 = r + dy;
@@ -143,10 +145,6 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
       const bool merged = rb1 >= 0 && gx >= nx_p && gx < nx_p + N;
       if (!merged) og = jb.obj[(size_t)(ny_n + r) * jb.W + gx];
     }
-  }
-  if (has_next && r == 0 && tid == 0) {
-    box_cur[0] = ny_n;
-    box_cur[1] = nx_n;
   }
   load_twiddles<N>(tw);
 
