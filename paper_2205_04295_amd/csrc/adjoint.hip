@@ -64,36 +64,64 @@ __device__ __forceinline__ float2 ramp(int ky, int kx, float fy, float fx, float
   return make_float2(cs, sn);
 }
 
+// Column passes work on CW adjacent columns per workgroup, so every global
+// access moves CW * 8 contiguous bytes of a row; pixel q of the group is row
+// k = q / CW, column c = q % CW (consecutive threads: consecutive columns).
+constexpr int kAdjCW1 = 8;  // passes with one transform per column
+constexpr int kAdjCWM = 4;  // the mode pass (M transforms per column)
+
+__device__ __forceinline__ int col_group(int nunits) {
+  return (nunits & 7) == 0 ? xcd_unit(blockIdx.x, nunits) : (int)blockIdx.x;
+}
+
 // P2 (cols): F(crop) -> F(o) = F(crop) e^{+2 pi i k.f/N}; stores F(o)
 // (unnormalised) and the inverse column pass of F(o)/N^2 into Cp
 template <int N>
 __device__ void adj_p2(const AdjArgs& a, float2* smem) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y;
-  if (u >= N) return;
-  const int j = a.j0 + b;
+  constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
+  const int u = col_group(gridDim.x), b = blockIdx.y;
+  if (u >= N / CW) return;
+  const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
   float fy, fx;
   frac_of(a, j, N, &fy, &fx);
   float2* tw = smem;
-  float2* A = tw + N;
-  float2* B = A + N;
-  const int k = threadIdx.x;
+  float2* A = tw + N;       // transform c at c * N
+  float2* B = A + CW * N;
   float2* cp = a.Cp + chunk_off(b, N);
-  float2 v = make_float2(0.f, 0.f);
-  if (k < N) v = cp[(size_t)k * N + u];
+  float2 v[PIX];
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    v[i] = cp[(size_t)k * N + u0 + c];
+  }
   load_twiddles<N>(tw);
-  if (k < N) A[k] = v;
-  __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, 1, tw);
-  float2* G = (F == A) ? B : A;
-  if (k < N) {
-    const int ky = k < N / 2 ? k : k - N, kx = u < N / 2 ? u : u - N;
-    const float2 fo = cmul(F[k], ramp(ky, kx, fy, fx, 1.f, N));
-    a.Fo[chunk_off(b, N) + (size_t)k * N + u] = fo;
-    G[k] = cscale(fo, 1.f / ((float)N * (float)N));
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, 1, tw);
-  if (k < N) cp[(size_t)k * N + u] = H[k];
+  float2* F = fft_lds<N, false>(A, B, CW, tw);
+  float2* G = (F == A) ? B : A;
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
+    if (q >= N * CW) continue;
+    const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
+    const float2 fo = cmul(F[c * N + k], ramp(ky, kx, fy, fx, 1.f, N));
+    a.Fo[chunk_off(b, N) + (size_t)k * N + uc] = fo;
+    G[c * N + k] = cscale(fo, 1.f / ((float)N * (float)N));
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true>(G, F, CW, tw);
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    cp[(size_t)k * N + u0 + c] = H[c * N + k];
+  }
 }
 
 // P3 (rows): o row r; exit waves P_p o, row FFTs -> Psi
@@ -138,61 +166,65 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
 // P4 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
 template <int N>
 __device__ void adj_p4(const AdjArgs& a, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES;
-  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y, M = a.M;
-  if (u >= N) return;
-  const int j = a.j0 + b;
+  constexpr int MM = MRPIE_MAX_MODES, CW = kAdjCWM, PIX = (N * CW + 255) / 256;
+  const int u = col_group(gridDim.x), b = blockIdx.y, M = a.M;
+  if (u >= N / CW) return;
+  const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
-  float2* A = tw + N;        // M N
-  float2* B = A + M * N;     // M N
+  float2* A = tw + N;          // transform (p, c) at (p * CW + c) * N
+  float2* B = A + M * CW * N;
   __shared__ double redd[16];
-  const int k = threadIdx.x;
   float2* psi = a.Psi + (size_t)b * M * NN;
-  float2 v[MM];
-  float Iv = 0.f;
-  if (k < N) {
-    Iv = a.I[(size_t)j * NN + (size_t)k * N + u];
+  const float* Ij = a.I + (size_t)j * NN;
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    const size_t off = (size_t)k * N + u0 + c;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) v[p] = psi[p * NN + (size_t)k * N + u];
+      if (p < M) A[(p * CW + c) * N + k] = psi[p * NN + off];
   }
   load_twiddles<N>(tw);
-  if (k < N) {
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) A[p * N + k] = v[p];
-  }
   __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, M, tw);
+  float2* F = fft_lds<N, false>(A, B, M * CW, tw);
   float2* G = (F == A) ? B : A;
   double e = 0.0;
-  if (k < N) {
-    const float invN = 1.f / (float)N;
+  const float invN = 1.f / (float)N;
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
     float S = 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) S += cabs2(F[p * N + k]);
+      if (p < M) S += cabs2(F[(p * CW + c) * N + k]);
     const float Au = sqrtf(S);
-    const float sq = sqrtf(fmaxf(Iv, 0.f));
+    const float sq = sqrtf(fmaxf(Ij[(size_t)k * N + u0 + c], 0.f));
     const float d = Au * invN - sq;
-    e = (double)d * (double)d;
+    e += (double)d * (double)d;
     // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
     // inverse 2-D transform
     const float wgt = Au > 0.f ? (1.f - sq * (float)N / Au) * invN * invN : 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) G[p * N + k] = cscale(F[p * N + k], wgt);
+      if (p < M) G[(p * CW + c) * N + k] = cscale(F[(p * CW + c) * N + k], wgt);
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, M, tw);
-  if (k < N) {
+  float2* H = fft_lds<N, true>(G, F, M * CW, tw);
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    const size_t off = (size_t)k * N + u0 + c;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + (size_t)k * N + u] = H[p * N + k];
+      if (p < M) psi[p * NN + off] = H[(p * CW + c) * N + k];
   }
   e = block_sum(e, redd);
-  if (threadIdx.x == 0) a.loss_part[(size_t)b * N + u] = e;
+  // one partial per column group, in the slot of its first column
+  if (tid < CW) a.loss_part[(size_t)b * N + u0 + tid] = tid == 0 ? e : 0.0;
 }
 
 // P5 (rows): chi row r; probe-gradient terms 2 conj(o) chi_p (kept per
@@ -246,47 +278,64 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
 // P6 (cols): F(g); position-gradient partials; S_{-f}: x e^{-2 pi i k.f/N}/N^2
 template <int N>
 __device__ void adj_p6(const AdjArgs& a, float2* smem) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x), b = blockIdx.y;
-  if (u >= N) return;
-  const int j = a.j0 + b;
+  constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
+  const int u = col_group(gridDim.x), b = blockIdx.y;
+  if (u >= N / CW) return;
+  const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
   float fy, fx;
   frac_of(a, j, N, &fy, &fx);
   float2* tw = smem;
   float2* A = tw + N;
-  float2* B = A + N;
+  float2* B = A + CW * N;
   __shared__ double redd[16];
-  const int k = threadIdx.x;
   float2* g = a.G + chunk_off(b, N);
-  float2 v = make_float2(0.f, 0.f), fo = v;
-  if (k < N) {
-    v = g[(size_t)k * N + u];
-    fo = a.Fo[chunk_off(b, N) + (size_t)k * N + u];
+  const float2* Fo = a.Fo + chunk_off(b, N);
+  float2 v[PIX];
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    v[i] = g[(size_t)k * N + u0 + c];
   }
   load_twiddles<N>(tw);
-  if (k < N) A[k] = v;
-  __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, 1, tw);
-  float2* G2 = (F == A) ? B : A;
-  double gy = 0.0, gx = 0.0;
-  if (k < N) {
-    const int ky = k < N / 2 ? k : k - N, kx = u < N / 2 ? u : u - N;
-    const float2 fg = F[k];
-    // Re conj(Fg) (i w) Fo = -w Im(conj(Fg) Fo), w = 2 pi k / N; unitary
-    // spectra are the unnormalised ones / N
-    const float2 cf = cmulc(fo, fg);  // Fo conj(Fg)
-    const double im = (double)cf.y / ((double)N * (double)N);
-    gy = -2.0 * M_PI * (double)ky / (double)N * im;
-    gx = -2.0 * M_PI * (double)kx / (double)N * im;
-    G2[k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G2, F, 1, tw);
-  if (k < N) g[(size_t)k * N + u] = H[k];
+  float2* F = fft_lds<N, false>(A, B, CW, tw);
+  float2* G2 = (F == A) ? B : A;
+  double gy = 0.0, gx = 0.0;
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
+    if (q >= N * CW) continue;
+    const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
+    const float2 fg = F[c * N + k];
+    // Re conj(Fg) (i w) Fo = -w Im(conj(Fg) Fo), w = 2 pi k / N; unitary
+    // spectra are the unnormalised ones / N
+    const float2 cf = cmulc(Fo[(size_t)k * N + uc], fg);  // Fo conj(Fg)
+    const double im = (double)cf.y / ((double)N * (double)N);
+    gy += -2.0 * M_PI * (double)ky / (double)N * im;
+    gx += -2.0 * M_PI * (double)kx / (double)N * im;
+    G2[c * N + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true>(G2, F, CW, tw);
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    g[(size_t)k * N + u0 + c] = H[c * N + k];
+  }
   gy = block_sum(gy, redd);
   gx = block_sum(gx, redd);
-  if (threadIdx.x == 0 && a.subpixel) {
-    a.pos_part[((size_t)b * N + u) * 2] = gy;
-    a.pos_part[((size_t)b * N + u) * 2 + 1] = gx;
+  // one partial per column group, in the slot of its first column
+  if (tid < CW && a.subpixel) {
+    a.pos_part[((size_t)b * N + u0 + tid) * 2] = tid == 0 ? gy : 0.0;
+    a.pos_part[((size_t)b * N + u0 + tid) * 2 + 1] = tid == 0 ? gx : 0.0;
   }
 }
 
@@ -331,9 +380,18 @@ MRPIE_ADJ_KERNEL(k_adj_p7, adj_p7)
 // loss += sum over the chunk's (position, column) partials, in order
 __global__ __launch_bounds__(256) void k_adj_loss(const AdjArgs a, int nb) {
   __shared__ double red[16];
-  double v = 0.0;
+  // eight independent partial sums per thread (loads in flight together),
+  // combined in a fixed order
+  double v8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int n = nb * a.N;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += a.loss_part[i];
+  for (int i0 = 0; i0 < n; i0 += 8 * 256) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q * 256 + threadIdx.x;
+      if (i < n) v8[q] += a.loss_part[i];
+    }
+  }
+  double v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
   v = block_sum(v, red);
   if (threadIdx.x == 0) *a.loss_acc += v;
 }
@@ -456,24 +514,27 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     hipLaunchKernelGGL(k_adj_zero, dim3(2048), dim3(256), 0, s, gobj, (size_t)pb->H * pb->W, (double*)nullptr);
     hipLaunchKernelGGL(k_adj_zero, dim3(256), dim3(256), 0, s, gprobe, (size_t)M * N * N, (double*)nullptr);
   }
+  // LDS of the row passes (one / M+1 / M transforms), of the single-field
+  // column passes (kAdjCW1 transforms) and of the mode column pass
   const size_t l1 = (size_t)3 * N * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
-  if (lm1 > 65536) {
-    MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
-    MRPIE_HIP(ensure_lds((const void*)k_adj_p4, lm1));
-    MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm1));
-  }
+  const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * N) * 8, lcm = (size_t)(N + 2 * M * kAdjCWM * N) * 8;
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p2, lc1));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p6, lc1));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p4, lcm));
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
-    const dim3 g(N, nb), blk(256);
+    const dim3 g(N, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(256);
     hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
-    hipLaunchKernelGGL(k_adj_p2, g, blk, l1, s, a);
+    hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
-    launch_k(TK_ADJ, k_adj_p4, g, blk, lm, s, a);
+    launch_k(TK_ADJ, k_adj_p4, gm, blk, lcm, s, a);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), blk, 0, s, a, nb);
     if (grads) {
       hipLaunchKernelGGL(k_adj_p5, g, blk, lm, s, a);
-      hipLaunchKernelGGL(k_adj_p6, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_p6, g1, blk, lc1, s, a);
       hipLaunchKernelGGL(k_adj_p7, g, blk, l1, s, a);
       hipLaunchKernelGGL(k_adj_pos, dim3(nb), blk, 0, s, a, nb);
       hipLaunchKernelGGL(k_adj_probe, dim3(512), blk, 0, s, a, nb);

@@ -74,33 +74,54 @@ __global__ __launch_bounds__(256) void k_reg_rows(const RegArgs a) {
   for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = R[i];
 }
 
+// CW adjacent columns per workgroup, so every access moves CW * 16
+// contiguous bytes of a row; pixel q of the group is row k = q / CW, column
+// c = q % CW.  LDS (dynamic): twiddles, then two ping-pong buffers of 2 CW
+// transforms (ref and mov of each column).
+constexpr int kRegCW = 4;
+constexpr size_t reg_cols_lds(int N) { return (size_t)(N + 2 * 2 * kRegCW * N) * 16; }
+
 template <int N>
 __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
-  __shared__ double2 tw[N];
-  __shared__ double2 A[2 * N], B[2 * N];
-  const int c = blockIdx.x, b = blockIdx.y;
+  constexpr int CW = kRegCW, PIX = (N * CW + 255) / 256;
+  extern __shared__ double2 dsm[];
+  double2* tw = dsm;
+  double2* A = tw + N;           // ref column c at c * N, mov at (CW + c) * N
+  double2* B = A + 2 * CW * N;
+  const int u0 = blockIdx.x * CW, b = blockIdx.y, tid = threadIdx.x;
   double2* w0 = a.work + (size_t)b * 2 * N * N;  // ref spectra -> later F^-1 over columns of X
   double2* w1 = w0 + (size_t)N * N;              // mov spectra -> later X
   load_twiddles<N>(tw);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    A[i] = w0[(size_t)i * N + c];
-    A[N + i] = w1[(size_t)i * N + c];
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    A[c * N + k] = w0[(size_t)k * N + u0 + c];
+    A[(CW + c) * N + k] = w1[(size_t)k * N + u0 + c];
   }
   __syncthreads();
-  double2* F = fft_lds<N, false>(A, B, 2, tw);
+  double2* F = fft_lds<N, false>(A, B, 2 * CW, tw);
   double2* G = (F == A) ? B : A;
-  for (int k = threadIdx.x; k < N; k += blockDim.x) {
-    double2 x = cmulc(F[k], F[N + k]);  // F(ref) conj(F(mov))
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    double2 x = cmulc(F[c * N + k], F[(CW + c) * N + k]);  // F(ref) conj(F(mov))
     if (a.norm) {
       const double m = hypot(x.x, x.y);
       x = m > 0.0 ? make_double2(x.x / m, x.y / m) : make_double2(0.0, 0.0);
     }
-    w1[(size_t)k * N + c] = x;
-    G[k] = x;
+    w1[(size_t)k * N + u0 + c] = x;
+    G[c * N + k] = x;
   }
   __syncthreads();
-  double2* H = fft_lds<N, true>(G, F, 1, tw);
-  for (int k = threadIdx.x; k < N; k += blockDim.x) w0[(size_t)k * N + c] = H[k];
+  double2* H = fft_lds<N, true>(G, F, CW, tw);
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    w0[(size_t)k * N + u0 + c] = H[c * N + k];
+  }
 }
 
 template <int N>
@@ -379,6 +400,7 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
   a.s0 = (int*)(ws + L.s0);
   a.tile_v = (double*)(ws + L.tile_v);
   a.tile_i = (long long*)(ws + L.tile_i);
+  MRPIE_HIP(ensure_lds((const void*)k_reg_cols<N>, reg_cols_lds(N)));
   hipLaunchKernelGGL(k_reg_kmat, dim3(64), dim3(256), 0, s, a, N);
   const int gt = (U + G2_T - 1) / G2_T;
   for (int b0 = 0; b0 < B; b0 += L.chunk) {
@@ -389,7 +411,7 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
     a.shift = shift + 2 * (size_t)b0;
     a.peak = peak + 4 * (size_t)b0;
     hipLaunchKernelGGL(k_reg_rows<N>, dim3(N, nb, 2), dim3(256), 0, s, a);
-    launch_k(TK_REG, k_reg_cols<N>, dim3(N, nb), dim3(256), 0, s, a);
+    launch_k(TK_REG, k_reg_cols<N>, dim3(N / kRegCW, nb), dim3(256), reg_cols_lds(N), s, a);
     hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_s0, dim3(nb), dim3(256), 0, s, a, N);
     launch_k(TK_GEMM, k_reg_gemm1<N>, dim3((N + G1_TX - 1) / G1_TX, (U + G1_TU - 1) / G1_TU, nb), dim3(256), 0, s, a);
