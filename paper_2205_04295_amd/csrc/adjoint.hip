@@ -227,52 +227,65 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
   if (tid < CW) a.loss_part[(size_t)b * N + u0 + tid] = tid == 0 ? e : 0.0;
 }
 
-// P5 (rows): chi row r; probe-gradient terms 2 conj(o) chi_p (kept per
-// position for the ordered reduction); g = 2 sum_p conj(P_p) chi_p, row FFT
+// P5 (rows): chi row r; g = 2 sum_p conj(P_p) chi_p, row FFT.  A workgroup
+// takes row r of kAdjGroup consecutive positions in order and sums their
+// probe-gradient terms 2 conj(o) chi_p in registers; the group's partial
+// replaces row r of its first position's Psi (which only this workgroup
+// reads), so the probe gradient is reduced from one array per group.
+constexpr int kAdjGroup = 8;
+
 template <int N>
 __device__ void adj_p5(const AdjArgs& a, float2* smem) {
   constexpr int MM = MRPIE_MAX_MODES;
-  const int r = blockIdx.x, b = blockIdx.y, M = a.M;
+  const int r = blockIdx.x, M = a.M;
+  const int b0 = blockIdx.y * kAdjGroup, b1 = min(b0 + kAdjGroup, a.nb);
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
   float2* A = tw + N;       // M N
   float2* B = A + M * N;    // M N
   const int c = threadIdx.x;
-  float2* psi = a.Psi + (size_t)b * M * NN;
-  float2 v[MM], P[MM];
-  float2 o = make_float2(0.f, 0.f);
-  if (c < N) {
-    o = a.Cp[chunk_off(b, N) + (size_t)r * N + c];
+  const size_t roff = (size_t)r * N + c;
+  float2 P[MM], acc[MM];
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) {
-        v[p] = psi[p * NN + (size_t)r * N + c];
-        P[p] = a.probe[p * NN + (size_t)r * N + c];
-      }
+  for (int p = 0; p < MM; ++p) {
+    acc[p] = make_float2(0.f, 0.f);
+    if (p < M && c < N) P[p] = a.probe[p * NN + roff];
   }
   load_twiddles<N>(tw);
+  for (int b = b0; b < b1; ++b) {
+    float2* psi = a.Psi + (size_t)b * M * NN;
+    float2 o = make_float2(0.f, 0.f);
+    if (c < N) {
+      o = a.Cp[chunk_off(b, N) + roff];
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) A[p * N + c] = psi[p * NN + roff];
+    }
+    __syncthreads();
+    float2* R = fft_lds<N, true>(A, B, M, tw);
+    float2* W = (R == A) ? B : A;
+    if (c < N) {
+      float2 g = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          const float2 chi = R[p * N + c];
+          acc[p] = cadd(acc[p], cscale(cmulc(chi, o), 2.f));   // 2 chi conj(o)
+          g = cadd(g, cmulc(chi, P[p]));
+        }
+      W[c] = cscale(g, 2.f);
+    }
+    __syncthreads();
+    float2* S = fft_lds<N, false>(W, R, 1, tw);
+    if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
+    __syncthreads();  // A, B are reused by the next position
+  }
   if (c < N) {
+    float2* part = a.Psi + (size_t)b0 * M * NN;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) A[p * N + c] = v[p];
+      if (p < M) part[p * NN + roff] = acc[p];
   }
-  __syncthreads();
-  float2* R = fft_lds<N, true>(A, B, M, tw);
-  float2* W = (R == A) ? B : A;
-  if (c < N) {
-    float2 g = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) {
-        const float2 chi = R[p * N + c];
-        psi[p * NN + (size_t)r * N + c] = cscale(cmulc(chi, o), 2.f);   // 2 chi conj(o)
-        g = cadd(g, cmulc(chi, P[p]));
-      }
-    W[c] = cscale(g, 2.f);
-  }
-  __syncthreads();
-  float2* S = fft_lds<N, false>(W, R, 1, tw);
-  if (c < N) a.G[chunk_off(b, N) + (size_t)r * N + c] = S[c];
 }
 
 // P6 (cols): F(g); position-gradient partials; S_{-f}: x e^{-2 pi i k.f/N}/N^2
@@ -413,12 +426,12 @@ __global__ __launch_bounds__(256) void k_adj_pos(const AdjArgs a, int nb) {
   }
 }
 
-// grad_P += sum_b (2 chi conj(o))_b over the chunk, in position order
+// grad_P += the chunk's group partials of 2 chi conj(o), in position order
 __global__ __launch_bounds__(256) void k_adj_probe(const AdjArgs a, int nb) {
   const size_t MNN = (size_t)a.M * a.N * a.N;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < MNN; i += (size_t)gridDim.x * blockDim.x) {
     float2 s = a.grad_probe[i];
-    for (int b = 0; b < nb; ++b) s = cadd(s, a.Psi[(size_t)b * MNN + i]);
+    for (int b = 0; b < nb; b += kAdjGroup) s = cadd(s, a.Psi[(size_t)b * MNN + i]);
     a.grad_probe[i] = s;
   }
 }
@@ -526,6 +539,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
+    a.nb = nb;
     const dim3 g(N, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(256);
     hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
@@ -533,7 +547,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     launch_k(TK_ADJ, k_adj_p4, gm, blk, lcm, s, a);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), blk, 0, s, a, nb);
     if (grads) {
-      hipLaunchKernelGGL(k_adj_p5, g, blk, lm, s, a);
+      hipLaunchKernelGGL(k_adj_p5, dim3(N, (nb + kAdjGroup - 1) / kAdjGroup), blk, lm, s, a);
       hipLaunchKernelGGL(k_adj_p6, g1, blk, lc1, s, a);
       hipLaunchKernelGGL(k_adj_p7, g, blk, l1, s, a);
       hipLaunchKernelGGL(k_adj_pos, dim3(nb), blk, 0, s, a, nb);

@@ -8,7 +8,7 @@ namespace mrpie {
 constexpr int kAdjChunk = 256;  // positions processed per pass
 
 struct AdjArgs {
-  int H, W, N, M, J, subpixel, j0;
+  int H, W, N, M, J, subpixel, j0, nb;  // nb: positions in the current chunk
   const float2* obj;
   const float2* probe;
   const float* pos;
@@ -17,7 +17,8 @@ struct AdjArgs {
   float2* Cp;          // [chunk][N][N] crop spectra -> o
   float2* Fo;          // [chunk][N][N] F(o), unnormalised
   float2* G;           // [chunk][N][N] g -> S_{-f}(g)
-  float2* Psi;         // [chunk][M][N][N] Psi -> chi -> 2 chi conj(o)
+  float2* Psi;         // [chunk][M][N][N] Psi -> chi; slot of each group's first
+                       // position -> the group's probe-gradient partial
   double* loss_part;   // [chunk][N]
   double* pos_part;    // [chunk][N][2]
   double* loss_acc;
