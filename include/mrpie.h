@@ -168,12 +168,15 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * FFT in LDS for the whole call; other jobs run the row / column passes
  * (default: 8 for N = 32, 1 for N = 64, 0 otherwise); cols_width: 1 or 4
  * adjacent detector columns per column-pass workgroup (1: shortest latency
- * for a single sweep; 4: coalesced 32-byte row segments, for batches).  The
+ * for a single sweep; 4: coalesced 32-byte row segments, for batches);
+ * rows_inplace: 1 runs the inverse row FFTs of multi-job launches in place
+ * (half the row pass's LDS: more workgroups per CU, one more barrier per
+ * FFT stage), 0 ping-pongs two buffers.  The
  * setting is process-wide host state; results do not depend on it beyond
  * float rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
  * candidates on the device and installs the fastest with mrpie_set_tuning. */
 typedef struct {
-  int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width;
+  int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width, rows_inplace;
 } mrpie_tuning;
 int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
 int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);

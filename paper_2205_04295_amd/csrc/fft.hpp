@@ -183,4 +183,66 @@ __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
   return a;
 }
 
+// In-place variant: every thread first reads the inputs of all of its
+// butterflies into registers, the workgroup synchronises, then every thread
+// writes its outputs over the same buffer — one buffer instead of two, at
+// the price of a second barrier per stage.  MAXB bounds the butterflies per
+// thread (nb * N / R / blockDim.x, rounded up).
+template <int N, int R, int NS, bool INV, int MAXB, typename C>
+__device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restrict__ tw) {
+  constexpr int Q = N / R;
+  constexpr int TWS = N / (NS * R);
+  const int total = nb * Q;
+  C v[MAXB][R];
+  int bs[MAXB], jj[MAXB];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int t = threadIdx.x + i * blockDim.x;
+    bs[i] = 0;
+    jj[i] = 0;
+    if (t < total) {
+      const int b = t / Q, j = t - b * Q;
+      bs[i] = b * N;
+      jj[i] = j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[b * N + j + r * Q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int t = threadIdx.x + i * blockDim.x;
+    if (t < total) {
+      const int j = jj[i];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * k * TWS];
+          if constexpr (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dftR<R, INV>(v[i]);
+      const int o = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[bs[i] + o + r * NS] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full in-place transforms of `nb` (<= MAXNB) contiguous rows of `buf`
+// with at least `MINT` threads per workgroup.  Same contract as fft_lds;
+// the result is in `buf`.
+template <int N, bool INV, bool R4, int MAXNB, int MINT, typename C>
+__device__ void fft_lds_inplace(C* buf, int nb, const C* __restrict__ tw) {
+  using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
+  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT>(buf, nb, tw);
+  stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT>(buf, nb, tw);
+  if constexpr (R2 > 1) stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT>(buf, nb, tw);
+  if constexpr (R3 > 1) stage_inplace<N, R3, R0 * R1 * R2, INV, (MAXNB * (N / R3) + MINT - 1) / MINT>(buf, nb, tw);
+}
+
 }  // namespace mrpie

@@ -41,7 +41,9 @@ namespace mrpie {
 // select one of a pair without dynamic indexing (keeps the layout in SGPRs)
 __device__ __forceinline__ size_t pick(const size_t (&a)[2], int i) { return i ? a[1] : a[0]; }
 
-template <int N, bool R4, int MM>
+// IP: the inverse row FFTs run in place (one 3MN buffer instead of two:
+// more workgroups per CU, one more barrier per stage) — for batches.
+template <int N, bool R4, int MM, bool IP = false>
 __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
   const int M = jb.M;
   const int total = jb.J * jb.T;
@@ -59,7 +61,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   float2* tw = smem;               // N
   float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
   float2* bufA = orow + N;         // 3*M*N
-  float2* bufB = bufA + 3 * M * N; // 3*M*N
+  float2* bufB = IP ? bufA + M * N : bufA + 3 * M * N;  // forward-FFT partner (IP: inside bufA)
   __shared__ float redf[32];
 
   const float2* psi_prev = (const float2*)(ws + pick(L.psi, prv));
@@ -163,7 +165,13 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     }
     float omax, pmaxv;
     block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
-    float2* res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
+    float2* res;
+    if constexpr (IP) {
+      fft_lds_inplace<N, true, R4, 3 * MM, 256>(bufA, ns * M, tw);
+      res = bufA;
+    } else {
+      res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
+    }
 
     // ---- probe update of row r (Eq. 5) from the pre-update o and P
     const int it_abs = cm.iter_offset + (t - 1) / jb.J;
@@ -360,16 +368,16 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
 // (jobs of the launch have M <= MM), so small M does not pay the register
 // cost (and occupancy) of the largest.
-template <bool R4, int MM>
+template <bool R4, int MM, bool IP>
 __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
   switch (jb.N) {
-    case 32: rows_body<32, R4, MM>(a.c, jb, t, smem); break;
-    case 64: rows_body<64, R4, MM>(a.c, jb, t, smem); break;
-    case 128: rows_body<128, R4, MM>(a.c, jb, t, smem); break;
-    case 192: rows_body<192, R4, MM>(a.c, jb, t, smem); break;
-    default: rows_body<256, R4, MM>(a.c, jb, t, smem); break;
+    case 32: rows_body<32, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 64: rows_body<64, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 128: rows_body<128, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 192: rows_body<192, R4, MM, IP>(a.c, jb, t, smem); break;
+    default: rows_body<256, R4, MM, IP>(a.c, jb, t, smem); break;
   }
 }
 
@@ -424,13 +432,13 @@ using ColsKernel1 = void (*)(char*, const float*, int, int, int, int, int*);
 
 static int mode_class(int M) { return M <= 1 ? 1 : M <= 2 ? 2 : M <= 4 ? 4 : 8; }
 
-template <bool R4>
+template <bool R4, bool IP>
 static SweepKernel pick_rows(int mc) {
   switch (mc) {
-    case 1: return k_rows<R4, 1>;
-    case 2: return k_rows<R4, 2>;
-    case 4: return k_rows<R4, 4>;
-    default: return k_rows<R4, 8>;
+    case 1: return k_rows<R4, 1, IP>;
+    case 2: return k_rows<R4, 2, IP>;
+    case 4: return k_rows<R4, 4, IP>;
+    default: return k_rows<R4, 8, IP>;
   }
 }
 template <bool R4, int CW>
@@ -468,8 +476,10 @@ static ColsKernel1 cols_kernel1(int radix, int width, int M) {
   if (width == 4) return radix == 8 ? pick_cols1<false, 4>(mc) : pick_cols1<true, 4>(mc);
   return radix == 8 ? pick_cols1<false, 1>(mc) : pick_cols1<true, 1>(mc);
 }
-static SweepKernel rows_kernel(int radix, int maxM) {
-  return radix == 8 ? pick_rows<false>(mode_class(maxM)) : pick_rows<true>(mode_class(maxM));
+static SweepKernel rows_kernel(int radix, bool inplace, int maxM) {
+  const int mc = mode_class(maxM);
+  if (inplace) return radix == 8 ? pick_rows<false, true>(mc) : pick_rows<true, true>(mc);
+  return radix == 8 ? pick_rows<false, false>(mc) : pick_rows<true, false>(mc);
 }
 static SweepKernel cols_kernel(int radix, int width, int maxM) {
   const int mc = mode_class(maxM);
@@ -546,7 +556,9 @@ __global__ void k_probe_back(const LaunchArgs a) {
 // CU's vector ALUs and LDS bandwidth bound the one-workgroup sweep; one
 // detector column per column workgroup for a single sweep (19.5 against
 // 23.3 us per position at 256^2 x 3), four in batches (8 jobs: 52.1 against
-// 57.2 us per lock-step position, 32 jobs: 168 against 182 us).  The
+// 57.2 us per lock-step position, 32 jobs: 168 against 182 us); in-place
+// inverse row FFTs in batches (8 jobs: 45.4 against 49.7 us, 32 jobs: 140
+// against 164 us), ping-pong for a single sweep.  The
 // autotuner measures the alternatives on the device for any (N, M, batch).
 static Tuning g_tune[4][2];
 static bool g_tune_set[4][2];
@@ -557,7 +569,7 @@ Tuning get_tuning(int N, int M, int nb) {
   (void)M;
   const int ni = n_index(N), bc = batch_class(nb);
   if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
-  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1};
+  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1, bc ? 1 : 0};
 }
 
 void set_tuning(int N, int nb, const Tuning& t) {
@@ -568,7 +580,7 @@ void set_tuning(int N, int nb, const Tuning& t) {
 }
 
 // ------------------------------------------------------------ host driver
-static size_t rows_lds(int N, int M) { return (size_t)(N + N + 6 * M * N) * 8; }
+static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 3 : 6) * M * N) * 8; }
 static size_t cols_lds(int N, int M, int cw) { return (size_t)(N + 2 * cw * M * N) * 8; }
 
 void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s) {
@@ -619,14 +631,15 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
       const JobRec& jb = jobs[c0 + b];
       maxN = std::max(maxN, jb.N);
       maxTot = std::max(maxTot, jb.J * jb.T);
-      lr = std::max(lr, rows_lds(jb.N, jb.M));
       eo.p[b] = err_out ? err_out[c0 + b] : nullptr;
     }
     const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
+    const bool ip = nb > 1 && tu.rows_inplace;
+    for (int b = 0; b < nb; ++b) lr = std::max(lr, rows_lds(a.job[b].N, a.job[b].M, ip));
     for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M, tu.cols_width));
     int maxM = 1;
     for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
-    const SweepKernel kr = rows_kernel(tu.rows_radix, maxM);
+    const SweepKernel kr = rows_kernel(tu.rows_radix, ip, maxM);
     const SweepKernel kc = cols_kernel(tu.cols_radix, tu.cols_width, maxM);
     MRPIE_HIP(ensure_lds((const void*)kr, lr));
     MRPIE_HIP(ensure_lds((const void*)kc, lc));
@@ -816,7 +829,9 @@ int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
   if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
   if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
   if (t->cols_width != 1 && t->cols_width != 4) return fail(MRPIE_EINVAL, "cols_width must be 1 or 4");
-  set_tuning(N, batched ? 2 : 1, Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width});
+  if (t->rows_inplace != 0 && t->rows_inplace != 1) return fail(MRPIE_EINVAL, "rows_inplace must be 0 or 1");
+  set_tuning(N, batched ? 2 : 1,
+             Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width, t->rows_inplace});
   return MRPIE_OK;
 }
 
@@ -829,6 +844,7 @@ int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
   t->rows_threads = u.rows_threads;
   t->lds_sweep = u.lds_sweep;
   t->cols_width = u.cols_width;
+  t->rows_inplace = u.rows_inplace;
   return MRPIE_OK;
 }
 

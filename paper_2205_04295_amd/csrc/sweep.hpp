@@ -74,6 +74,7 @@ struct Tuning {
   int lds_sweep;     // jobs with M <= lds_sweep whose modes fit the LDS run the
                      // one-workgroup sweep (0: never)
   int cols_width;    // 1 or 4 adjacent detector columns per column workgroup
+  int rows_inplace;  // 1: multi-job row passes run their inverse FFTs in place
 };
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);

@@ -16,10 +16,10 @@ import torch
 
 from . import _abi, api
 
-CANDIDATES = [dict(rows_radix=rr, cols_radix=cr, rows_threads=th, lds_sweep=0, cols_width=cw)
-              for rr, cr, th, cw in itertools.product((4, 8), (4, 8), (256, 512), (1, 4))]
-LDS_CANDIDATE = dict(rows_radix=8, cols_radix=8, rows_threads=256, lds_sweep=8, cols_width=1)
-_KEYS = ("rows_radix", "cols_radix", "rows_threads", "lds_sweep", "cols_width")
+CANDIDATES = [dict(rows_radix=rr, cols_radix=cr, rows_threads=th, lds_sweep=0, cols_width=cw, rows_inplace=ip)
+              for rr, cr, th, cw, ip in itertools.product((4, 8), (4, 8), (256, 512), (1, 4), (0, 1))]
+LDS_CANDIDATE = dict(rows_radix=8, cols_radix=8, rows_threads=256, lds_sweep=8, cols_width=1, rows_inplace=0)
+_KEYS = ("rows_radix", "cols_radix", "rows_threads", "lds_sweep", "cols_width", "rows_inplace")
 
 
 def lds_fits(N, M):
@@ -28,8 +28,8 @@ def lds_fits(N, M):
     return N <= 128 and M * N * N <= 16384
 
 
-def set_tuning(N, batched, rows_radix, cols_radix, rows_threads, lds_sweep=0, cols_width=1):
-    t = _abi.Tuning(rows_radix, cols_radix, rows_threads, lds_sweep, cols_width)
+def set_tuning(N, batched, rows_radix, cols_radix, rows_threads, lds_sweep=0, cols_width=1, rows_inplace=0):
+    t = _abi.Tuning(rows_radix, cols_radix, rows_threads, lds_sweep, cols_width, rows_inplace)
     _abi.check(_abi.load().mrpie_set_tuning(N, int(bool(batched)), C.byref(t)))
 
 

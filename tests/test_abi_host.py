@@ -107,16 +107,19 @@ def test_tuning_round_trip(lib):
     d = _abi.Tuning()
     assert lib.mrpie_get_tuning(128, 1, C.byref(d)) == 0
     assert (d.rows_radix, d.cols_radix, d.rows_threads, d.lds_sweep) == (8, 8, 256, 0)
-    assert d.cols_width in (1, 4)
+    assert (d.cols_width, d.rows_inplace) == (4, 1)  # batch class
+    d0 = _abi.Tuning()
+    assert lib.mrpie_get_tuning(128, 0, C.byref(d0)) == 0 and (d0.cols_width, d0.rows_inplace) == (1, 0)
     d64 = _abi.Tuning()
     assert lib.mrpie_get_tuning(64, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
-    t = _abi.Tuning(8, 4, 256, 0, 4)
+    t = _abi.Tuning(8, 4, 256, 0, 4, 1)
     assert lib.mrpie_set_tuning(128, 1, C.byref(t)) == 0
     u = _abi.Tuning()
     assert lib.mrpie_get_tuning(128, 1, C.byref(u)) == 0
-    assert (u.rows_radix, u.cols_radix, u.rows_threads, u.lds_sweep, u.cols_width) == (8, 4, 256, 0, 4)
+    assert (u.rows_radix, u.cols_radix, u.rows_threads, u.lds_sweep, u.cols_width, u.rows_inplace) == (8, 4, 256, 0, 4, 1)
     assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(5, 4, 256, 1, 1))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 9, 1))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 2))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 3))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(100, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
     assert lib.mrpie_set_tuning(128, 1, C.byref(d)) == 0  # restore the default

@@ -18,8 +18,9 @@ def _gpu():
     need_gpu()
 
 
-def test_batched_equals_plain_per_job():
-    from paper_2205_04295_amd import api
+@pytest.mark.parametrize("inplace", [0, 1])
+def test_batched_equals_plain_per_job(inplace):
+    from paper_2205_04295_amd import api, tune
     specs = [dict(seed=71, H=160, N=64, M=1, J=9), dict(seed=72, H=256, N=128, M=3, J=5),
              dict(seed=73, H=320, N=192, M=2, J=3), dict(seed=74, H=384, N=256, M=4, J=4),
              dict(seed=75, H=128, N=64, M=5, J=12)]
@@ -29,8 +30,14 @@ def test_batched_equals_plain_per_job():
     jobs = [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"],
                  err=torch.zeros(2, dtype=torch.float32, device="cuda:0"),
                  status=torch.zeros(1, dtype=torch.int32, device="cuda:0")) for d in devs]
-    api.rpie_batched(jobs, **prm)
-    torch.cuda.synchronize()
+    # the launch's tuning is that of its largest probe size, batch class
+    saved = tune.get_tuning(256, True)
+    try:
+        tune.set_tuning(256, True, **dict(saved, rows_inplace=inplace))
+        api.rpie_batched(jobs, **prm)
+        torch.cuda.synchronize()
+    finally:
+        tune.set_tuning(256, True, **saved)
     for w, j in zip(ws, jobs):
         g = run_gpu(w, prm)
         assert np.array_equal(j["obj"].cpu().numpy(), g["O"])

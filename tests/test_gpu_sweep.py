@@ -226,7 +226,8 @@ def test_every_launch_shape_matches_oracle(name):
     N = w.P0.shape[-1]
     saved = tune.get_tuning(N, False)
     try:
-        for cand in tune.CANDIDATES:
+        # rows_inplace only shapes multi-job launches
+        for cand in [c for c in tune.CANDIDATES if not c["rows_inplace"]]:
             tune.set_tuning(N, False, **cand)
             g = run_gpu(w, prm)
             assert rel_l2(g["O"], o["O"]) < 1e-4 and rel_l2(g["P"], o["P"]) < 1e-4, cand
