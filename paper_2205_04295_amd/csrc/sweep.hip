@@ -60,8 +60,8 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
 
   float2* tw = smem;               // N
   float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
-  float2* bufA = orow + N;         // 3*M*N
-  float2* bufB = IP ? bufA + M * N : bufA + 3 * M * N;  // forward-FFT partner (IP: inside bufA)
+  float2* bufA = orow + N;         // 2*M*N
+  float2* bufB = IP ? bufA + M * N : bufA + 2 * M * N;  // forward-FFT partner (IP: inside bufA)
   __shared__ float redf[32];
 
   const float2* psi_prev = (const float2*)(ws + pick(L.psi, prv));
@@ -73,9 +73,9 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   //      patch row and spectra and the max partials do not depend on the box
   //      geometry, so they are issued before the positions are even read;
   //      the rows that depend on the boxes follow.
-  float2 pv[3][MM];      // psi_prev rows (row-transformed spectra)
-  float2 Pq[3][MM];      // old probe at the slot rows
-  float2 oq[3];          // old patch at the slot rows
+  float2 pv[2][MM];      // psi_prev rows (row-transformed spectra)
+  float2 Pq[2][MM];      // old probe at the slot rows
+  float2 oq[2];          // old patch at the slot rows
   float2 og = make_float2(0.f, 0.f);  // object value of the next box row, outside the updated row
   float2 Ph[MM];         // probe row r when there is no previous step
   float om_in = 0.f, pm_in = 0.f, i_touch = 0.f;
@@ -125,13 +125,17 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
       rb1 = r;
     }
   }
-  // distinct box rows needing an inverse row FFT: slot 0 is the probe row r
+  // distinct box rows needing an inverse row FFT: slot 0 is the probe row r,
+  // slot 1 the box row that moves into the next box (rb1, when dy != 0 and
+  // r + dy is inside) or the one that leaves it (rb2, dy < 0 and r < -dy;
+  // for dy > 0 the leaving row is r itself).  The two cases exclude each
+  // other, so at most two rows are transformed.
   const bool u1 = rb1 >= 0 && rb1 != r, u2 = rb2 >= 0 && rb2 != r;
-  const int rows[3] = {r, u1 ? rb1 : rb2, rb2};
-  const int ns = has_prev ? 1 + (int)u1 + (int)u2 : 0;
+  const int rows[2] = {r, u1 ? rb1 : rb2};
+  const int ns = has_prev ? 1 + (int)(u1 || u2) : 0;
   if (lane) {
 #pragma unroll
-    for (int q = 1; q < 3; ++q) {
+    for (int q = 1; q < 2; ++q) {
       if (q >= ns) break;
       const size_t off = (size_t)rows[q] * N + c;
 #pragma unroll
@@ -156,7 +160,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   if (has_prev) {
     if (lane) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < 2; ++q) {
         if (q >= ns) break;
 #pragma unroll
         for (int p = 0; p < MM; ++p)
@@ -167,7 +171,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
     float2* res;
     if constexpr (IP) {
-      fft_lds_inplace<N, true, R4, 3 * MM, 256>(bufA, ns * M, tw);
+      fft_lds_inplace<N, true, R4, 2 * MM, 256>(bufA, ns * M, tw);
       res = bufA;
     } else {
       res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
@@ -198,7 +202,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     //      them is the probe row r, slots 1.. otherwise
     if (lane) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const bool is_obj = q == 0 ? (rb1 == r || rb2 == r) : (q < ns);
         if (!is_obj) continue;
         const int rb = rows[q];
@@ -580,7 +584,7 @@ void set_tuning(int N, int nb, const Tuning& t) {
 }
 
 // ------------------------------------------------------------ host driver
-static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 3 : 6) * M * N) * 8; }
+static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 2 : 4) * M * N) * 8; }
 static size_t cols_lds(int N, int M, int cw) { return (size_t)(N + 2 * cw * M * N) * 8; }
 
 void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s) {
