@@ -171,7 +171,8 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * for a single sweep; 4: coalesced 32-byte row segments, for batches);
  * rows_inplace: 1 runs the inverse row FFTs of multi-job launches in place
  * (half the row pass's LDS: more workgroups per CU, one more barrier per
- * FFT stage), 0 ping-pongs two buffers.  The
+ * FFT stage), and the column FFTs too from 16 jobs per launch on (with
+ * cols_width 4); 0 ping-pongs two buffers.  The
  * setting is process-wide host state; results do not depend on it beyond
  * float rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
  * candidates on the device and installs the fastest with mrpie_set_tuning. */

@@ -62,3 +62,23 @@ def test_batched_more_jobs_than_one_launch():
     torch.cuda.synchronize()
     for j in jobs:
         assert np.array_equal(j["obj"].cpu().numpy(), ref["O"])
+
+
+def test_batched_many_jobs_in_place_passes():
+    """18 jobs in one launch (the column pass then runs in place as well):
+    each job's object and probe equal its plain sweep bitwise."""
+    from paper_2205_04295_amd import api
+    specs = [dict(seed=90 + i, H=192 if i % 2 else 256, N=128, M=1 + i % 3, J=3 + i % 4) for i in range(18)]
+    ws = [wl.small_case(name=f"m{i}", **s) for i, s in enumerate(specs)]
+    prm = dict(ws[0].params, iterations=2)
+    devs = [to_dev(w) for w in ws]
+    jobs = [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"]) for d in devs]
+    api.rpie_batched(jobs, **prm)
+    torch.cuda.synchronize()
+    for w, j in zip(ws, jobs):
+        g = run_gpu(w, prm)
+        assert np.array_equal(j["obj"].cpu().numpy(), g["O"])
+        assert np.array_equal(j["probe"].cpu().numpy(), g["P"])
+    o = run_oracle(ws[4], prm)
+    assert rel_l2(jobs[4]["obj"].cpu().numpy(), o["O"]) < 1e-4
+    assert rel_l2(jobs[4]["probe"].cpu().numpy(), o["P"]) < 1e-4
