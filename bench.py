@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--uneven", type=float, default=0.25,
                     help="scan-length scale of the 64-job uneven batch (0 = skip, 1 = full)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep launch shapes first")
+    ap.add_argument("--batch-large", type=int, default=32,
+                    help="also measure a batch of this many jobs (0: skip)")
     ap.add_argument("--small", type=int, default=1,
                     help="also time the 64^2 raster workload (LDS sweep vs row / column passes)")
     ap.add_argument("--calib", action="store_true",
@@ -104,11 +106,10 @@ def cpu_baseline(w, npos):
                 seconds=round(dt, 3))
 
 
-def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_b, cols_b):
+def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_b, cols_b, B):
     """B independent reconstructions of the same shape (each its own object,
     probe, workspace and a rotated copy of the scan and patterns), advanced
     lock-step in shared launches; aggregate positions x iterations / s."""
-    B = args.batch
     J = pos0.shape[0]
     jobs = []
     for b in range(B):
@@ -357,9 +358,12 @@ def main():
     # whole-path algorithmic bandwidth (all kernels of a step)
     path_gbs = (rows_b + cols_b) * J / (ms_per_step * 1e-3) / 1e9
 
-    batched = None
+    batched = batched_large = None
     if args.batch > 0:
-        batched = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b)
+        batched = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b, args.batch)
+    if args.batch_large > 0:
+        batched_large = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b,
+                                        args.batch_large)
 
     refine = measure_refine(api, torch, dev, args) if args.refine_iters > 0 else None
     adjoint = measure_adjoint(api, torch, dev, obj, probe, pos, I, args) if args.adjoint else None
@@ -407,6 +411,7 @@ def main():
         "eager": eager,
         "graph": graph_mode,
         "batched": batched,
+        "batched_large": batched_large,
         "refine": refine,
         "adjoint": adjoint,
         "uneven_batch": uneven,

@@ -57,6 +57,8 @@ def autotune(N, M, batch=1, J=64, reps=3, device="cuda:0", verbose=False):
     batched = batch > 1
     times = {}
     cands = CANDIDATES + ([LDS_CANDIDATE] if lds_fits(N, M) else [])
+    if not batched:  # the in-place option only shapes multi-job launches
+        cands = [c for c in cands if not c["rows_inplace"]]
     for cand in cands:
         set_tuning(N, batched, **cand)
         best = float("inf")

@@ -239,12 +239,13 @@ def test_autotuner_installs_a_candidate():
     from paper_2205_04295_amd import tune
     saved, saved256 = tune.get_tuning(64, False), tune.get_tuning(256, False)
     try:
+        single = [c for c in tune.CANDIDATES if not c["rows_inplace"]]
         best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
-        cands = tune.CANDIDATES + [tune.LDS_CANDIDATE]
+        cands = single + [tune.LDS_CANDIDATE]
         assert best in cands and len(times) == len(cands)
         assert tune.get_tuning(64, False) == best
         best, times = tune.autotune(256, 2, batch=1, J=4, reps=1)
-        assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
+        assert best in single and len(times) == len(single)
     finally:
         tune.set_tuning(64, False, **saved)
         tune.set_tuning(256, False, **saved256)
