@@ -68,18 +68,20 @@ def disc_probe(N, R, edge=2.0, phase_edge=0.5, with_phase=True):
     return amp * np.exp(1j * ph)
 
 
-MODE_POWERS = (0.7, 0.2, 0.1, 0.05, 0.025)
+MODE_POWERS = (0.7, 0.2, 0.1, 0.05, 0.025, 0.0125, 0.00625, 0.003125)
 
 
 def probe_modes(N, R, M, powers=None, with_phase=True):
-    """M mutually orthogonal modes {P0, P0 x/R, P0 y/R, P0 (x^2-y^2)/R^2,
-    P0 2xy/R^2}[:M], Gram-Schmidt orthogonalised, unit total power split by
-    `powers` (renormalised)."""
+    """M (<= 8) mutually orthogonal modes {P0, P0 x/R, P0 y/R,
+    P0 (x^2-y^2)/R^2, P0 2xy/R^2, P0 (x^3-3xy^2)/R^3, P0 (3x^2y-y^3)/R^3,
+    P0 (x^2+y^2)/R^2}[:M], Gram-Schmidt orthogonalised, unit total power
+    split by `powers` (renormalised)."""
     base = disc_probe(N, R, with_phase=with_phase)
     y, x = np.mgrid[0:N, 0:N].astype(np.float64)
     y = (y - N / 2) / R
     x = (x - N / 2) / R
-    mods = [np.ones_like(x), x, y, x * x - y * y, 2 * x * y][:M]
+    mods = [np.ones_like(x), x, y, x * x - y * y, 2 * x * y, x ** 3 - 3 * x * y * y, 3 * x * x * y - y ** 3,
+            x * x + y * y][:M]
     powers = np.asarray(powers if powers is not None else MODE_POWERS[:M], dtype=np.float64)
     powers = powers / powers.sum()
     out = []
@@ -257,26 +259,29 @@ def batch_jobs(seed=4, njobs=64, sizes=(64, 128, 192, 256), jmin=50, jmax=900,
 
 
 def small_case(seed, H, N, M, J, R=None, photons=1e6, subpixel=False, edges=True,
-               name="small"):
+               name="small", W=None):
     """Small workload for parity tests: Fermat spiral over the whole span,
     optionally with the first two positions pinned at the object corners
-    (ragged / edge boxes) and optional fractional positions."""
+    (ragged / edge boxes) and optional fractional positions.  The object is
+    H x W (W = H by default)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    W = H if W is None else W
     R = R if R is not None else N / 4.0
-    O = object_field(rng, H, H)
+    O = object_field(rng, H, W)
     P = probe_modes(N, R, M)
-    span = H - N
-    c = span / 2.0 / math.sqrt(max(J - 1, 1))
-    pos = fermat_spiral(J, c, (span / 2.0, span / 2.0))
+    sy, sx = H - N, W - N
+    c = min(sy, sx) / 2.0 / math.sqrt(max(J - 1, 1))
+    pos = fermat_spiral(J, c, (sy / 2.0, sx / 2.0))
     if edges and J >= 3:
-        pos[1] = (0.0, float(span))
-        pos[2] = (float(span), 0.0)
+        pos[1] = (0.0, float(sx))
+        pos[2] = (float(sy), 0.0)
+    lim = np.array([sy, sx], dtype=np.float64)
     if subpixel:
         pos = pos + rng.uniform(-0.45, 0.45, size=pos.shape)
-        pos = np.clip(pos, 0, span)
+        pos = np.clip(pos, 0, lim)
     else:
         pos = np.floor(pos + 0.5)
-    pos = np.clip(pos, 0, span)
+    pos = np.clip(pos, 0, lim)
     I, scale = simulate_patterns(rng, O, P, pos, photons, True)
     return _finish(name, O, P, pos, pos, I, scale, R,
                    dict(R1_PARAMS, subpixel=int(subpixel)), seed=seed)

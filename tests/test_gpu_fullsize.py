@@ -1,0 +1,78 @@
+"""Parity at the full 256^2 x 3-mode, 1600-position spiral workload (object
+1024^2), in the launch configuration the benchmark times.  The sweep is
+sequential, so full-size outputs are checked by teacher forcing: from the
+GPU's own state after k positions, one more position on the GPU and in the
+FP64 oracle must agree to float rounding; and a full iteration of a batched
+launch equals the single-job sweep of the same job bitwise."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import workloads as wl
+
+from gpu_util import need_gpu, rel_l2, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.fixture(scope="module")
+def spiral():
+    return wl.spiral_case(seed=1)
+
+
+def _prefix(w, k):
+    return wl.Workload(w.name, w.O_true, w.P_true, w.pos_true[:k], w.I[:k], w.O0, w.P0, w.pos0[:k], w.params)
+
+
+@pytest.mark.parametrize("k", [1, 777, 1599])
+def test_full_size_step_teacher_forced(spiral, k):
+    w = spiral
+    prm = dict(w.params, iterations=1)
+    st = run_gpu(_prefix(w, k), prm)
+    assert st["status"] == 0
+    step = wl.Workload(w.name, w.O_true, w.P_true, w.pos_true[k:k + 1], w.I[k:k + 1], st["O"], st["P"],
+                       w.pos0[k:k + 1], w.params)
+    g = run_gpu(step, prm)
+    ref = oracle.rpie64(st["O"], st["P"], w.pos0[k:k + 1], w.I[k:k + 1], oracle.Params(**prm))
+    ny, nx = (int(v) for v in np.floor(w.pos0[k] + 0.5))
+    N = w.P0.shape[-1]
+    box = (slice(ny, ny + N), slice(nx, nx + N))
+    # the step's change, which is what one position computes
+    dO_g, dO_o = g["O"][box] - st["O"][box], ref["O"][box] - st["O"][box]
+    dP_g, dP_o = g["P"] - st["P"], ref["P"] - st["P"]
+    e_box, e_dO, e_dP = rel_l2(g["O"][box], ref["O"][box]), rel_l2(dO_g, dO_o), rel_l2(dP_g, dP_o)
+    print(f"k={k}: box {e_box:.2e} dO {e_dO:.2e} dP {e_dP:.2e}")
+    assert e_box < 1e-5 and rel_l2(g["P"], ref["P"]) < 1e-5
+    assert e_dO < 2e-5 and e_dP < 2e-5
+    outside = np.ones(g["O"].shape, bool)
+    outside[box] = False
+    assert np.array_equal(g["O"][outside], st["O"][outside])
+
+
+def test_full_size_batch_equals_single_sweeps(spiral):
+    """Four full-size jobs (rotated scans) in one batched launch sequence:
+    jobs 0 and 3 equal their single-job sweeps bitwise in object and probe."""
+    from paper_2205_04295_amd import api
+    w = spiral
+    prm = dict(w.params)
+    prm.pop("iterations")
+    dev = torch.device("cuda:0")
+    J = w.pos0.shape[0]
+    O0, P0 = torch.from_numpy(w.O0).to(dev), torch.from_numpy(w.P0).to(dev)
+    pos0, I0 = torch.from_numpy(w.pos0).to(dev), torch.from_numpy(w.I).to(dev)
+    shifts = [(b * J) // 4 for b in range(4)]
+    jobs = [dict(obj=O0.clone(), probe=P0.clone(), pos=torch.roll(pos0, sh, 0).contiguous(),
+                 intens=torch.roll(I0, sh, 0).contiguous()) for sh in shifts]
+    api.rpie_batched(jobs, iterations=1, **prm)
+    torch.cuda.synchronize()
+    for b in (0, 3):
+        o, p = O0.clone(), P0.clone()
+        api.rpie(o, p, jobs[b]["pos"], jobs[b]["intens"], iterations=1, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(jobs[b]["obj"], o) and torch.equal(jobs[b]["probe"], p)

@@ -95,6 +95,31 @@ def test_lds_sweep_and_passes_one_iteration(name, lds):
     assert abs(g["err"][0] - o["err"][0]) <= 1e-4 * abs(o["err"][0])
 
 
+# the largest mode count (8) and non-square objects, through the passes
+# (including the row pass above 64 KiB of LDS at 256^2 x 8) and the LDS sweep
+EDGE_CASES = {
+    "n128m8_rect": (dict(seed=28, H=256, W=384, N=128, M=8, J=12), 0),
+    "n256m8_rect": (dict(seed=29, H=384, W=320, N=256, M=8, J=6), 0),
+    "n64m4_rect_lds": (dict(seed=30, H=128, W=224, N=64, M=4, J=20), 8),
+    "n32m8_lds": (dict(seed=31, H=96, W=80, N=32, M=8, J=16), 8),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE_CASES))
+def test_max_modes_and_rectangular_objects(name):
+    spec, lds = EDGE_CASES[name]
+    w = wl.small_case(name=name, **spec)
+    prm = dict(w.params, iterations=1)
+    with tuning(spec["N"], lds_sweep=lds):
+        g = run_gpu(w, prm)
+    o = run_oracle(w, prm)
+    assert g["status"] == 0
+    eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
+    print(f"{name}: rel L2 O {eo:.2e} P {ep:.2e}")
+    assert eo < 1e-4 and ep < 1e-4
+    assert abs(g["err"][0] - o["err"][0]) <= 1e-4 * abs(o["err"][0])
+
+
 def test_lds_sweep_is_bitwise_deterministic():
     w = wl.small_case(name="n64m3", **LDS_CASES["n64m3"])
     prm = dict(w.params, iterations=2)
