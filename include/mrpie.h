@@ -125,7 +125,12 @@ int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t
  *                   sum_j sum I for each iteration (may be NULL)
  *  status int32, OR-ed with MRPIE_STATUS_* bits (may be NULL)
  *  ws, ws_bytes     workspace of at least mrpie_workspace_size bytes
- * The result is deterministic: the same inputs give bitwise equal outputs. */
+ * The result is deterministic: the same inputs give bitwise equal outputs.
+ * With refine = 1 the registration of every block of 256 positions runs on
+ * an internal non-blocking stream (default priority) while the sweep goes
+ * on, joined back into `stream` before the Adam step; the first such call
+ * on a device creates that stream and 16 events, kept until the process
+ * ends.  No device memory is allocated. */
 int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void* probe,
                float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);

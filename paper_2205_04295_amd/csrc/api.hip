@@ -44,6 +44,35 @@ hipError_t ensure_lds(const void* kernel, size_t bytes) {
   return e;
 }
 
+// ------------------------------------------------------------ side stream
+// One non-blocking stream (default priority) and a ring of events per
+// device, created on first use, for work the library overlaps with a
+// latency-bound sweep on the caller's stream.
+namespace {
+constexpr int kMaxDevices = 16;
+struct Side {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[kSideEvents] = {};
+};
+Side g_side[kMaxDevices];
+std::mutex g_side_mu;
+}  // namespace
+
+int side_stream(hipStream_t* out, hipEvent_t** events) {
+  int dev = 0;
+  MRPIE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MRPIE_EDEVICE, "device %d beyond the side-stream table", dev);
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  Side& sd = g_side[dev];
+  if (!sd.stream) {
+    MRPIE_HIP(hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking));
+    for (int i = 0; i < kSideEvents; ++i) MRPIE_HIP(hipEventCreateWithFlags(&sd.ev[i], hipEventDisableTiming));
+  }
+  *out = sd.stream;
+  *events = sd.ev;
+  return MRPIE_OK;
+}
+
 // ------------------------------------------------------------ timing
 namespace {
 constexpr int kEvPairs = 8192;

@@ -184,6 +184,11 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // attribute; done outside any stream capture the first time a size is seen).
 hipError_t ensure_lds(const void* kernel, size_t bytes);
 
+// The current device's side stream (non-blocking, default priority) and
+// its ring of kSideEvents events (no timing), created on first use.
+constexpr int kSideEvents = 16;
+int side_stream(hipStream_t* out, hipEvent_t** events);
+
 // ---------------------------------------------------------------- timing
 // Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
 // launch of a timed kernel class is launched with hipExtLaunchKernelGGL and

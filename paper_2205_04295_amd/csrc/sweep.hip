@@ -769,18 +769,44 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
     float* shift = (float*)(jb.ws + R.shift);
     int32_t* peak = (int32_t*)(jb.ws + R.peak);
     const size_t reg_bytes = reg_layout(jb.N, jb.J, pr->upsample).total;
+    // The sweep is latency bound (one workgroup per row or column of one
+    // position per launch), so the registration of each block of
+    // kRegChunk positions runs on the side stream as soon as the sweep
+    // has recorded those pairs, on the CUs the sweep leaves idle; Adam
+    // waits for all of them at the end of the iteration.
+    hipStream_t s2 = nullptr;
+    hipEvent_t* ev = nullptr;
+    int evn = 0;
+    const size_t NN = (size_t)jb.N * jb.N;
     for (int it = 0; it < jb.T; ++it) {
-      rc = run_sweep_subpixel(c, jb, ex, it, 1, true, true, s);
-      if (rc) return rc;
       const int it_abs = pr->iter_offset + it;
-      if (it_abs >= pr->refine_start) {
-        rc = run_register(jb.N, jb.J, ex.reg_ref, ex.reg_mov, pr->upsample, pr->xcorr_norm, shift, peak,
-                          jb.ws + R.reg, reg_bytes, s);
+      if (it_abs < pr->refine_start) {
+        rc = run_sweep_subpixel(c, jb, ex, it, 1, true, true, s);
         if (rc) return rc;
-        rc = launch_adam(jb.J, (float*)jb.pos, adam, shift, it_abs - pr->refine_start + 1, pr, jb.H - jb.N,
-                         jb.W - jb.N, s);
+        continue;
+      }
+      if (!s2) {
+        rc = side_stream(&s2, &ev);
         if (rc) return rc;
       }
+      const int nch = (jb.J + kRegChunk - 1) / kRegChunk;
+      for (int k = 0; k < nch; ++k) {
+        const int p0 = k * kRegChunk, p1 = std::min(jb.J, p0 + kRegChunk);
+        rc = run_sweep_subpixel_range(c, jb, ex, it * jb.J + p0, it * jb.J + p1, k == 0, k == nch - 1, s);
+        if (rc) return rc;
+        hipEvent_t e = ev[evn++ % kSideEvents];
+        MRPIE_HIP(hipEventRecord(e, s));
+        MRPIE_HIP(hipStreamWaitEvent(s2, e, 0));
+        rc = run_register(jb.N, p1 - p0, ex.reg_ref + p0 * NN, ex.reg_mov + p0 * NN, pr->upsample, pr->xcorr_norm,
+                          shift + 2 * (size_t)p0, peak + 4 * (size_t)p0, jb.ws + R.reg, reg_bytes, s2);
+        if (rc) return rc;
+      }
+      hipEvent_t e = ev[evn++ % kSideEvents];
+      MRPIE_HIP(hipEventRecord(e, s2));
+      MRPIE_HIP(hipStreamWaitEvent(s, e, 0));
+      rc = launch_adam(jb.J, (float*)jb.pos, adam, shift, it_abs - pr->refine_start + 1, pr, jb.H - jb.N,
+                       jb.W - jb.N, s);
+      if (rc) return rc;
     }
   }
   float* eo[1] = {err_out};

@@ -90,6 +90,10 @@ struct SubpixelExtra {
 };
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s);
+// The same for position ticks [t0, t1) (t = iteration * J + position); head:
+// t0 starts a call (no previous step), tail: t1 ends it.
+int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int t0, int t1, bool head,
+                             bool tail, hipStream_t s);
 size_t rpie_ws_total(const mrpie_problem* pb, const mrpie_params* pr);
 int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr, float* adam, float* err_out,
                        hipStream_t s);

@@ -360,6 +360,11 @@ __global__ __launch_bounds__(256) void k_sp_update(const SpArgs a, int t) {
 
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s) {
+  return run_sweep_subpixel_range(c, jb, ex, it0 * jb.J, (it0 + iters) * jb.J, head, tail, s);
+}
+
+int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int t0, int t1, bool head,
+                             bool tail, hipStream_t s) {
   int rc = launch_init_twiddles(s);
   if (rc) return rc;
   SpArgs a{};
@@ -378,7 +383,6 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
   MRPIE_HIP(ensure_lds((const void*)k_sp_exit, le));
   MRPIE_HIP(ensure_lds((const void*)k_sp_update, lu));
   const dim3 g(N), blk(256);
-  const int t0 = it0 * jb.J, t1 = (it0 + iters) * jb.J;
   for (int t = t0; t < t1; ++t) {
     hipLaunchKernelGGL(k_sp_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
     hipLaunchKernelGGL(k_sp_ramp, g, blk, lr, s, a, t, 0);
