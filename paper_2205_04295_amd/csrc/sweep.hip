@@ -293,9 +293,13 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   float2* tw = smem;
   float2* bufA = tw + N;                // transform (p, c) at (p * CW + c) * N
   float2* bufB = IP ? bufA : bufA + M * CW * N;
-  // per-wave partial of the Fourier error (kErrSlots / 256 waves per unit)
-  double* err_slot = (double*)(jb.ws + L.err) + (size_t)it * kErrSlots + u * (NT / 64) + (tid >> 6);
+  // per-wave partials of the Fourier error and of the intensity sum that
+  // normalises it (kErrSlots / 256 waves per unit)
+  const size_t slot = (size_t)it * kErrSlots + u * (NT / 64) + (tid >> 6);
+  double* err_slot = (double*)(jb.ws + L.err) + slot;
+  double* isum_slot = (double*)(jb.ws + L.isum) + slot;
   const double err_old = (tid & 63) == 0 ? *err_slot : 0.0;
+  const double isum_old = (tid & 63) == 0 ? *isum_slot : 0.0;
   // pixel q = tid + NT * i of the group: row k = q / CW, column c = q % CW
   // (consecutive threads read consecutive columns of a row)
   float Iv[PIX];
@@ -335,13 +339,14 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   // Eq. 7: the 2-D transform here is unnormalised (N x unitary) and so is
   // the inverse, so the scale factor carries one 1/N.
   const float invN = 1.0f / (float)N;
-  double e = 0.0;
+  double e = 0.0, isv = 0.0;
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + NT * i;
     if (q < N * CW) {
       const int k = q / CW, c = q - k * CW;
+      isv += (double)fmaxf(Iv[i], 0.f);
       float S = 0.f;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
@@ -380,7 +385,11 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
     }
   }
   e = wave_sum(e);
-  if ((tid & 63) == 0) *err_slot = err_old + e;
+  isv = wave_sum(isv);
+  if ((tid & 63) == 0) {
+    *err_slot = err_old + e;
+    *isum_slot = isum_old + isv;
+  }
 }
 
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
@@ -512,44 +521,37 @@ __global__ void k_zero_err(const LaunchArgs a) {
   const JobRec& jb = a.job[blockIdx.y];
   const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
   double* e = (double*)(jb.ws + L.err);
+  double* is = (double*)(jb.ws + L.isum);
   const size_t n = (size_t)(jb.T > 0 ? jb.T : 1) * kErrSlots;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) e[i] = 0.0;
-}
-
-// per-job partial sums of max(I, 0), fixed order (blockIdx.x = part)
-__global__ __launch_bounds__(256) void k_isum_partial(const LaunchArgs a) {
-  __shared__ double red[16];
-  const JobRec& jb = a.job[blockIdx.y];
-  const size_t n = (size_t)jb.J * jb.N * jb.N;
-  double v = 0.0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    v += (double)fmaxf(jb.I[i], 0.f);
-  v = block_sum(v, red);
-  const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
-  if (threadIdx.x == 0) ((double*)(jb.ws + L.isum))[blockIdx.x] = v;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    e[i] = 0.0;
+    is[i] = 0.0;
+  }
 }
 
 struct ErrOut {
   float* p[kMaxJobsPerLaunch];
 };
 
-// err_out[it] = sum of the per-column partials / sum of the intensities
+// err_out[it] = sum of the iteration's error partials / sum of its
+// intensity partials (both accumulated by the column passes)
 __global__ __launch_bounds__(256) void k_finish(const LaunchArgs a, const ErrOut eo) {
   __shared__ double red[16];
   const JobRec& jb = a.job[blockIdx.y];
   const WsLayout L = ws_layout(jb.N, jb.M, jb.T);
   float* out = eo.p[blockIdx.y];
   if (!out) return;
-  const double* part = (const double*)(jb.ws + L.isum);
-  double v = 0.0;
-  for (int i = threadIdx.x; i < kIsumParts; i += blockDim.x) v += part[i];
-  const double isum = block_sum(v, red);
   const double* err = (const double*)(jb.ws + L.err);
+  const double* isp = (const double*)(jb.ws + L.isum);
   for (int t = 0; t < jb.T; ++t) {
-    double e = 0.0;
-    for (int i = threadIdx.x; i < kErrSlots; i += blockDim.x) e += err[(size_t)t * kErrSlots + i];
+    double e = 0.0, v = 0.0;
+    for (int i = threadIdx.x; i < kErrSlots; i += blockDim.x) {
+      e += err[(size_t)t * kErrSlots + i];
+      v += isp[(size_t)t * kErrSlots + i];
+    }
     e = block_sum(e, red);
-    if (threadIdx.x == 0) out[t] = (float)(isum > 0.0 ? e / isum : e);
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) out[t] = (float)(v > 0.0 ? e / v : e);
   }
 }
 
@@ -638,7 +640,6 @@ void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream
   ErrOut eo{};
   for (int b = 0; b < nb; ++b) eo.p[b] = err_out ? err_out[b] : nullptr;
   if (probe_back) hipLaunchKernelGGL(k_probe_back, dim3(64, nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_finish, dim3(1, nb), dim3(256), 0, s, a, eo);
 }
 
@@ -695,7 +696,6 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
       }
     }
     hipLaunchKernelGGL(k_probe_back, dim3(64, nb), blk, 0, s, a);
-    hipLaunchKernelGGL(k_isum_partial, dim3(kIsumParts, nb), blk, 0, s, a);
     hipLaunchKernelGGL(k_finish, dim3(1, nb), blk, 0, s, a, eo);
     MRPIE_HIP(hipGetLastError());
   }

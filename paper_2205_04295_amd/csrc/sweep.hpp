@@ -6,7 +6,6 @@
 namespace mrpie {
 
 constexpr int kErrSlots = 1024;  // per-iteration error partials (one per wave of each column unit)
-constexpr int kIsumParts = 256;  // partial sums of the intensities
 constexpr int kMaxJobsPerLaunch = 36;
 
 // Parameters shared by all jobs of one call.
@@ -58,7 +57,7 @@ __host__ __device__ inline WsLayout ws_layout(int N, int M, int T) {
   MRPIE_TAKE(L.box[0], 16)
   MRPIE_TAKE(L.box[1], 16)
   MRPIE_TAKE(L.err, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)
-  MRPIE_TAKE(L.isum, (size_t)kIsumParts * 8)
+  MRPIE_TAKE(L.isum, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)  // same slots: sums of max(I, 0)
   MRPIE_TAKE(L.cb, NN * 8)   // subpixel path: shifted-crop spectra
   MRPIE_TAKE(L.db, NN * 8)   // subpixel path: object-update spectra
 #undef MRPIE_TAKE

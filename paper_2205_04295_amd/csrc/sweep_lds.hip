@@ -156,6 +156,7 @@ __device__ __forceinline__ void lds_sweep_body(const Common& cm, const JobRec& j
   load_twiddles<N>(tw);
   const WsLayout L = ws_layout(N, M, jb.T);
   double* errs = (double*)(jb.ws + L.err);
+  double* isums = (double*)(jb.ws + L.isum);
   const float invN = 1.0f / (float)N;
 
   // the probe modes at this thread's pixels, for the whole call
@@ -167,7 +168,7 @@ __device__ __forceinline__ void lds_sweep_body(const Common& cm, const JobRec& j
 
   for (int it = 0; it < jb.T; ++it) {
     const bool upd_p = cm.iter_offset + it >= cm.probe_update_start;
-    double eacc = 0.0;
+    double eacc = 0.0, iacc = 0.0;
     for (int j = 0; j < J; ++j) {
       const int ny = box_corner(jb.pos[2 * j], H - N, jb.status);
       const int nx = box_corner(jb.pos[2 * j + 1], W - N, jb.status);
@@ -231,6 +232,7 @@ __device__ __forceinline__ void lds_sweep_body(const Common& cm, const JobRec& j
         const float sq = __builtin_amdgcn_sqrtf(fmaxf(KEEP ? Iv[k] : Ij[i], 0.f));
         const float d = Au * invN - sq;
         eacc += (double)d * (double)d;
+        iacc += (double)fmaxf(KEEP ? Iv[k] : Ij[i], 0.f);
         bad |= !isfinite(S);
         const float f = sq * rs * invN;
 #pragma unroll
@@ -272,7 +274,11 @@ __device__ __forceinline__ void lds_sweep_body(const Common& cm, const JobRec& j
       __syncthreads();
     }
     eacc = block_sum(eacc, redd);
-    if (tid0 == 0) errs[(size_t)it * kErrSlots] = eacc;
+    iacc = block_sum(iacc, redd);
+    if (tid0 == 0) {
+      errs[(size_t)it * kErrSlots] = eacc;
+      isums[(size_t)it * kErrSlots] = iacc;
+    }
   }
 #pragma unroll
   for (int p = 0; p < MM; ++p)
