@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "2973b45aecf89b16110d6a873c0266935a7cf1ac1a086cd136cd7f8f66c78012",
+    "sha256": "58c0a2fc7373a02209f3b8bee4355728a19dd0caf6354fc9987d9bd49da399ae",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    "k_rows": {"fetch_kib": 3465.0, "write_kib": 4097.6},
-    "k_cols": {"fetch_kib": 984.5, "write_kib": 1544.0},
+    "k_rows": {"fetch_kib": 3453.5, "write_kib": 4097.6},
+    "k_cols": {"fetch_kib": 990.0, "write_kib": 1552.0},
 }
 
 
