@@ -390,21 +390,23 @@ MRPIE_ADJ_KERNEL(k_adj_p6, adj_p6)
 MRPIE_ADJ_KERNEL(k_adj_p7, adj_p7)
 
 // ---------------------------------------------------------------- reductions
-// loss += sum over the chunk's (position, column) partials, in order
-__global__ __launch_bounds__(256) void k_adj_loss(const AdjArgs a, int nb) {
+// loss += sum over the chunk's (position, column) partials, in order: each
+// of kLossBlocks workgroups sums one contiguous range, then one workgroup
+// adds the range sums
+constexpr int kLossBlocks = 64;
+__global__ __launch_bounds__(256) void k_adj_loss_part(const AdjArgs a, int nb) {
   __shared__ double red[16];
-  // eight independent partial sums per thread (loads in flight together),
-  // combined in a fixed order
-  double v8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const int n = nb * a.N;
-  for (int i0 = 0; i0 < n; i0 += 8 * 256) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = i0 + q * 256 + threadIdx.x;
-      if (i < n) v8[q] += a.loss_part[i];
-    }
-  }
-  double v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
+  const int n = nb * a.N, per = (n + kLossBlocks - 1) / kLossBlocks;
+  const int i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+  double v = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) v += a.loss_part[i];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) a.loss_blk[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(64) void k_adj_loss(const AdjArgs a) {
+  __shared__ double red[16];
+  double v = a.loss_blk[threadIdx.x];
   v = block_sum(v, red);
   if (threadIdx.x == 0) *a.loss_acc += v;
 }
@@ -500,6 +502,7 @@ AdjLayout adj_layout(int N, int M, int J) {
   L.Psi = take((size_t)B * M * NN * 8);
   L.loss_part = take((size_t)B * N * 8);
   L.pos_part = take((size_t)B * N * 16);
+  L.loss_blk = take((size_t)kLossBlocks * 8);
   L.loss_acc = take(16);
   L.total = off;
   return L;
@@ -520,6 +523,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   a.obj = obj; a.probe = probe; a.pos = pos; a.I = intens; a.status = status;
   a.Cp = (float2*)(w + L.Cp); a.Fo = (float2*)(w + L.Fo); a.G = (float2*)(w + L.G); a.Psi = (float2*)(w + L.Psi);
   a.loss_part = (double*)(w + L.loss_part); a.pos_part = (double*)(w + L.pos_part);
+  a.loss_blk = (double*)(w + L.loss_blk);
   a.loss_acc = (double*)(w + L.loss_acc);
   a.grad_obj = gobj; a.grad_probe = gprobe; a.grad_pos = gpos;
   hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, s, (float2*)nullptr, (size_t)0, a.loss_acc);
@@ -545,7 +549,8 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
     launch_k(TK_ADJ, k_adj_p4, gm, blk, lcm, s, a);
-    hipLaunchKernelGGL(k_adj_loss, dim3(1), blk, 0, s, a, nb);
+    hipLaunchKernelGGL(k_adj_loss_part, dim3(kLossBlocks), blk, 0, s, a, nb);
+    hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(kLossBlocks), 0, s, a);
     if (grads) {
       hipLaunchKernelGGL(k_adj_p5, dim3(N, (nb + kAdjGroup - 1) / kAdjGroup), blk, lm, s, a);
       hipLaunchKernelGGL(k_adj_p6, g1, blk, lc1, s, a);

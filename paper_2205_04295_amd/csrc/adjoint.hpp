@@ -21,6 +21,7 @@ struct AdjArgs {
                        // position -> the group's probe-gradient partial
   double* loss_part;   // [chunk][N]
   double* pos_part;    // [chunk][N][2]
+  double* loss_blk;    // [kLossBlocks] partial sums of loss_part
   double* loss_acc;
   float2* grad_obj;
   float2* grad_probe;
@@ -29,7 +30,7 @@ struct AdjArgs {
 
 struct AdjLayout {
   int chunk;
-  size_t Cp, Fo, G, Psi, loss_part, pos_part, loss_acc, total;
+  size_t Cp, Fo, G, Psi, loss_part, pos_part, loss_blk, loss_acc, total;
 };
 
 AdjLayout adj_layout(int N, int M, int J);
