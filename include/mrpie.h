@@ -154,10 +154,11 @@ typedef struct {
  * refine and subpixel must be 0) on `njobs` independent reconstructions of
  * any mix of N, M, J and object size, lock-step by position: every launch
  * advances one position of every unfinished job, so one pair of launches
- * carries the work of all jobs.  Each job's object and probe are bitwise
- * equal to those of a mrpie_rpie call on that job alone when both use the
- * same FFT radices (the defaults do); the error curve may differ in the
- * summation order of its partial sums.  `jobs` is a HOST array read during
+ * carries the work of all jobs.  Each job's object and probe match those
+ * of a mrpie_rpie call on that job alone to float rounding (the single-job
+ * column pass keeps its first and last FFT stages in registers; jobs that
+ * run the one-workgroup LDS sweep in both are bitwise equal); the error
+ * curve may differ in the summation order of its partial sums.  `jobs` is a HOST array read during
  * the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
 

@@ -392,6 +392,136 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   }
 }
 
+// Column pass of one column with the first and last FFT stages in
+// registers (radix-8 plans, N >= 128, one column per workgroup): the
+// forward transform's first stage takes the global loads directly, its
+// last stage leaves each thread j < N/RL every mode at the frequencies
+// j + (N/RL) r, so the mode-summed modulus (Eq. 7) and the first inverse
+// stage need no LDS round trip, and the inverse transform's last stage
+// stores straight to global memory: four barriers instead of eight.
+template <int N, int MM>
+__device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* smem) {
+  using P = Plan8<N>;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2];
+  static_assert(R2 > 1 && P::R[3] == 1, "three-stage plans only");
+  constexpr int RL = R2;           // last forward radix = first inverse radix
+  constexpr int Q0 = N / R0;       // butterflies per transform of the first stage
+  constexpr int QL = N / RL;       // threads of the mode-sum stage
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
+  if (t >= total) return;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  if (u >= N) return;
+  const int it = t / jb.J, jn = t - it * jb.J;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  const size_t NN = (size_t)N * N;
+  float2* psi = (float2*)(jb.ws + pick(L.psi, t & 1));
+  const float* Ij = jb.I + (size_t)jn * NN;
+  const int tid = threadIdx.x;
+
+  float2* tw = smem;
+  float2* bufA = tw + N;           // M N
+  float2* bufB = bufA + M * N;     // M N
+
+  const size_t slot = (size_t)it * kErrSlots + u * 4 + (tid >> 6);
+  double* err_slot = (double*)(jb.ws + L.err) + slot;
+  double* isum_slot = (double*)(jb.ws + L.isum) + slot;
+  const double err_old = (tid & 63) == 0 ? *err_slot : 0.0;
+  const double isum_old = (tid & 63) == 0 ? *isum_slot : 0.0;
+
+  // first-stage inputs (thread (p, j): rows j + Q0 r of mode p) and the
+  // patterns of the mode-sum threads
+  const bool s0 = tid < M * Q0;
+  const int p0 = tid / Q0, j0 = tid - p0 * Q0;
+  float2 v[R0];
+  if (s0) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = psi[p0 * NN + (size_t)(j0 + Q0 * r) * N + u];
+  }
+  float Iv[RL];
+  if (tid < QL) {
+#pragma unroll
+    for (int r = 0; r < RL; ++r) Iv[r] = Ij[(size_t)(tid + QL * r) * N + u];
+  }
+  load_twiddles<N>(tw);
+  // forward stage 1 (no twiddles) -> LDS
+  if (s0) {
+    dftR<R0, false>(v);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) bufA[p0 * N + j0 * R0 + r] = v[r];
+  }
+  __syncthreads();
+  // forward stage 2, LDS -> LDS
+  stage<N, R1, R0, false>(bufA, bufB, M, tw);
+  __syncthreads();
+  // forward stage 3 (every mode per thread), modulus, inverse stage 1
+  double e = 0.0, isv = 0.0;
+  if (tid < QL) {
+    float2 X[MM][RL];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) X[p][r] = bufB[p * N + tid + QL * r];
+#pragma unroll
+        for (int r = 1; r < RL; ++r) X[p][r] = cmul(X[p][r], tw[r * tid]);
+        dftR<RL, false>(X[p]);
+      }
+    const float invN = 1.0f / (float)N;
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      float S = 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) S += cabs2(X[p][r]);
+      const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+      const float Au = S * rs;
+      const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv[r], 0.f));
+      const float d = Au * invN - sq;
+      e += (double)d * (double)d;
+      isv += (double)fmaxf(Iv[r], 0.f);
+      bad |= !isfinite(S);
+      const float f = sq * rs * invN;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) X[p][r] = cscale(X[p][r], f);
+    }
+    if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        dftR<RL, true>(X[p]);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) bufA[p * N + tid * RL + r] = X[p][r];
+      }
+  }
+  __syncthreads();
+  // inverse stage 2, LDS -> LDS
+  stage<N, R1, RL, true>(bufA, bufB, M, tw);
+  __syncthreads();
+  // inverse stage 3 -> global
+  if (s0) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = bufB[p0 * N + j0 + Q0 * r];
+#pragma unroll
+    for (int r = 1; r < R0; ++r) {
+      float2 w = tw[r * j0];
+      w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dftR<R0, true>(v);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) psi[p0 * NN + (size_t)(j0 + Q0 * r) * N + u] = v[r];
+  }
+  e = wave_sum(e);
+  isv = wave_sum(isv);
+  if ((tid & 63) == 0) {
+    *err_slot = err_old + e;
+    *isum_slot = isum_old + isv;
+  }
+}
+
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
 // (jobs of the launch have M <= MM), so small M does not pay the register
 // cost (and occupancy) of the largest.
@@ -443,12 +573,24 @@ template <bool R4, int MM, int CW>
 __global__ __launch_bounds__(256) void k_cols1(char* ws, const float* I, int t, int J, int T, int NM, int* status) {
   extern __shared__ float2 smem[];
   const JobRec jb{nullptr, nullptr, nullptr, I, ws, status, 0, 0, NM & 0xffff, NM >> 16, J, T};
+  // radix-8 plans with one column per workgroup: stages in registers at
+  // both ends from N = 128 on
+  constexpr bool RD = !R4 && CW == 1;
   switch (jb.N) {
     case 32: cols_body<32, R4, MM, CW>(jb, t, smem); break;
     case 64: cols_body<64, R4, MM, CW>(jb, t, smem); break;
-    case 128: cols_body<128, R4, MM, CW>(jb, t, smem); break;
-    case 192: cols_body<192, R4, MM, CW>(jb, t, smem); break;
-    default: cols_body<256, R4, MM, CW>(jb, t, smem); break;
+    case 128:
+      if constexpr (RD) cols_body_rd<128, MM>(jb, t, smem);
+      else cols_body<128, R4, MM, CW>(jb, t, smem);
+      break;
+    case 192:
+      if constexpr (RD) cols_body_rd<192, MM>(jb, t, smem);
+      else cols_body<192, R4, MM, CW>(jb, t, smem);
+      break;
+    default:
+      if constexpr (RD) cols_body_rd<256, MM>(jb, t, smem);
+      else cols_body<256, R4, MM, CW>(jb, t, smem);
+      break;
   }
 }
 

@@ -1,7 +1,8 @@
 """Batched M-rPIE: independent reconstructions of uneven N, M, J advanced
-lock-step in shared launches must each equal the plain sweep bitwise in
-object and probe (the error curve to summation order), and the oracle to
-the plain sweep's tolerance."""
+lock-step in shared launches must each match the plain sweep of the same job
+to float rounding (the single-job column pass keeps its first and last FFT
+stages in registers; jobs on the same kernels — the LDS sweep — are bitwise
+equal), and the oracle to the plain sweep's tolerance."""
 import numpy as np
 import pytest
 import torch
@@ -40,10 +41,11 @@ def test_batched_equals_plain_per_job(inplace):
         tune.set_tuning(256, True, **saved)
     for w, j in zip(ws, jobs):
         g = run_gpu(w, prm)
-        assert np.array_equal(j["obj"].cpu().numpy(), g["O"])
-        assert np.array_equal(j["probe"].cpu().numpy(), g["P"])
-        # the error curve's partial sums group detector columns differently
-        assert np.allclose(j["err"].cpu().numpy(), g["err"], rtol=1e-6, atol=0)
+        assert rel_l2(j["obj"].cpu().numpy(), g["O"]) < 1e-5
+        assert rel_l2(j["probe"].cpu().numpy(), g["P"]) < 1e-5
+        if w.P0.shape[-1] == 64 and w.P0.shape[0] == 1:  # LDS sweep in both
+            assert np.array_equal(j["obj"].cpu().numpy(), g["O"])
+        assert np.allclose(j["err"].cpu().numpy(), g["err"], rtol=1e-5, atol=0)
         assert int(j["status"].item()) == 0
     o = run_oracle(ws[1], prm)
     assert rel_l2(jobs[1]["obj"].cpu().numpy(), o["O"]) < 1e-4
@@ -66,7 +68,7 @@ def test_batched_more_jobs_than_one_launch():
 
 def test_batched_many_jobs_in_place_passes():
     """18 jobs in one launch (the column pass then runs in place as well):
-    each job's object and probe equal its plain sweep bitwise."""
+    each job's object and probe match its plain sweep to float rounding."""
     from paper_2205_04295_amd import api
     specs = [dict(seed=90 + i, H=192 if i % 2 else 256, N=128, M=1 + i % 3, J=3 + i % 4) for i in range(18)]
     ws = [wl.small_case(name=f"m{i}", **s) for i, s in enumerate(specs)]
@@ -77,8 +79,8 @@ def test_batched_many_jobs_in_place_passes():
     torch.cuda.synchronize()
     for w, j in zip(ws, jobs):
         g = run_gpu(w, prm)
-        assert np.array_equal(j["obj"].cpu().numpy(), g["O"])
-        assert np.array_equal(j["probe"].cpu().numpy(), g["P"])
+        assert rel_l2(j["obj"].cpu().numpy(), g["O"]) < 1e-5
+        assert rel_l2(j["probe"].cpu().numpy(), g["P"]) < 1e-5
     o = run_oracle(ws[4], prm)
     assert rel_l2(jobs[4]["obj"].cpu().numpy(), o["O"]) < 1e-4
     assert rel_l2(jobs[4]["probe"].cpu().numpy(), o["P"]) < 1e-4

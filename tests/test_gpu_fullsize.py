@@ -3,7 +3,7 @@
 sequential, so full-size outputs are checked by teacher forcing: from the
 GPU's own state after k positions, one more position on the GPU and in the
 FP64 oracle must agree to float rounding; and a full iteration of a batched
-launch equals the single-job sweep of the same job bitwise."""
+launch matches the single-job sweep of the same job to float rounding."""
 import numpy as np
 import pytest
 import torch
@@ -57,7 +57,9 @@ def test_full_size_step_teacher_forced(spiral, k):
 
 def test_full_size_batch_equals_single_sweeps(spiral):
     """Four full-size jobs (rotated scans) in one batched launch sequence:
-    jobs 0 and 3 equal their single-job sweeps bitwise in object and probe."""
+    jobs 0 and 3 match their single-job sweeps (the single job's column pass
+    keeps its first and last FFT stages in registers, so the two differ only
+    in the rounding of fused multiply-adds)."""
     from paper_2205_04295_amd import api
     w = spiral
     prm = dict(w.params)
@@ -75,4 +77,7 @@ def test_full_size_batch_equals_single_sweeps(spiral):
         o, p = O0.clone(), P0.clone()
         api.rpie(o, p, jobs[b]["pos"], jobs[b]["intens"], iterations=1, **prm)
         torch.cuda.synchronize()
-        assert torch.equal(jobs[b]["obj"], o) and torch.equal(jobs[b]["probe"], p)
+        eo = rel_l2(jobs[b]["obj"].cpu().numpy(), o.cpu().numpy())
+        ep = rel_l2(jobs[b]["probe"].cpu().numpy(), p.cpu().numpy())
+        print(f"job {b}: batch vs single rel L2 O {eo:.2e} P {ep:.2e}")
+        assert eo < 1e-5 and ep < 1e-5
