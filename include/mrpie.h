@@ -17,7 +17,9 @@
  *    matching *_workspace_size function returns (0 when none is needed).
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
  *    default stream) and performs no host<->device synchronisation and no
- *    allocation, so it may be recorded into a HIP graph.
+ *    device-memory allocation, so it may be recorded into a HIP graph (the
+ *    refining sweep also forks work to an internal stream and joins it
+ *    back, see mrpie_rpie).
  *  - The object O is [H][W]; probe modes P are [M][N][N]; positions are
  *    [J][2] floats (y, x): the top-left corner of the N x N box in object
  *    pixels; diffraction intensities are [J][N][N] in FFT order (zero
@@ -43,7 +45,7 @@ extern "C" {
 
 #define MRPIE_OK 0
 #define MRPIE_EINVAL (-1)       /* bad shape, parameter or null pointer */
-#define MRPIE_EUNSUPPORTED (-2) /* N not in {64,128,192,256} or M > 8 */
+#define MRPIE_EUNSUPPORTED (-2) /* N not in {32,64,128,192,256} or M > 8 */
 #define MRPIE_EDEVICE (-3)      /* HIP runtime error (message in mrpie_last_error) */
 #define MRPIE_EWORKSPACE (-4)   /* workspace missing or too small */
 
@@ -54,8 +56,8 @@ extern "C" {
 
 #define MRPIE_MAX_MODES 8
 
-/* Problem shape.  H, W: object rows / columns; N: probe side (64, 128, 192
- * or 256); M: number of mutually incoherent probe modes (1..8, Eq. 4);
+/* Problem shape.  H, W: object rows / columns; N: probe side (32, 64, 128,
+ * 192 or 256); M: number of mutually incoherent probe modes (1..8, Eq. 4);
  * J: number of scan positions. */
 typedef struct {
   int32_t H, W, N, M, J;
@@ -189,7 +191,7 @@ int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
 int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);
 
 /* Test hook: in-place unitary 2-D DFT (D_z, Eq. 2; inverse = 1 gives
- * D_{-z}) of B contiguous N x N complex64 arrays.  N in {64,128,192,256}. */
+ * D_{-z}) of B contiguous N x N complex64 arrays.  N in {32,64,128,192,256}. */
 int mrpie_fft2(int32_t N, int32_t B, void* data, int32_t inverse, void* stream);
 
 /* Test hook: in-place modulus replacement of Eq. 7 on M detector-plane
@@ -247,9 +249,12 @@ int mrpie_adjoint(const mrpie_problem* pb, int32_t subpixel, const void* obj, co
 
 /* Diagnostic kernel timing (not for use under graph capture).
  * mrpie_timing_enable(stride): from now on, every stride-th launch of each
- * timed kernel class is bracketed by a HIP event pair on the stream it is
- * launched on (stride = 0 switches timing off).  Classes: 0 = sweep row
- * pass (k_rows), 1 = sweep column pass (k_cols).
+ * timed kernel class is launched with a start / stop event pair of its own
+ * dispatch (hipExtLaunchKernelGGL) on the stream it is launched on (stride
+ * = 0 switches timing off).  Classes: 0 = sweep row pass (k_rows, k_rows1),
+ * 1 = sweep column pass (k_cols, k_cols1), 2 = registration column pass
+ * (k_reg_cols), 3 = registration window GEMM (k_reg_gemm1), 4 = adjoint
+ * modulus pass (k_adj_p4), 5 = one-workgroup LDS sweep (k_lds_sweep).
  * mrpie_timing_read(avg_ms[nkinds], count[nkinds], nkinds): waits for the
  * recorded events, returns the mean duration and number of timed launches
  * per class, and clears the record.  Host-side state, one per process. */

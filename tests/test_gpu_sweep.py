@@ -18,7 +18,7 @@ def _gpu():
     need_gpu()
 
 
-@pytest.mark.parametrize("N", [64, 128, 192, 256])
+@pytest.mark.parametrize("N", [32, 64, 128, 192, 256])
 def test_fft2_matches_unitary_dft(N):
     from paper_2205_04295_amd import api
     rng = np.random.default_rng(N)
