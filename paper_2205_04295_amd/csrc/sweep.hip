@@ -542,12 +542,22 @@ template <bool R4, int MM, int CW, bool IP>
 __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
+  constexpr bool RD = !R4 && CW == 1 && !IP;
   switch (jb.N) {
     case 32: cols_body<32, R4, MM, CW, IP>(jb, t, smem); break;
     case 64: cols_body<64, R4, MM, CW, IP>(jb, t, smem); break;
-    case 128: cols_body<128, R4, MM, CW, IP>(jb, t, smem); break;
-    case 192: cols_body<192, R4, MM, CW, IP>(jb, t, smem); break;
-    default: cols_body<256, R4, MM, CW, IP>(jb, t, smem); break;
+    case 128:
+      if constexpr (RD) cols_body_rd<128, MM>(jb, t, smem);
+      else cols_body<128, R4, MM, CW, IP>(jb, t, smem);
+      break;
+    case 192:
+      if constexpr (RD) cols_body_rd<192, MM>(jb, t, smem);
+      else cols_body<192, R4, MM, CW, IP>(jb, t, smem);
+      break;
+    default:
+      if constexpr (RD) cols_body_rd<256, MM>(jb, t, smem);
+      else cols_body<256, R4, MM, CW, IP>(jb, t, smem);
+      break;
   }
 }
 
