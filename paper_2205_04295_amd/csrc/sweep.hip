@@ -764,26 +764,6 @@ static size_t cols_lds(int N, int M, int cw, bool inplace) { return (size_t)(N +
 // 41.1 us).
 constexpr int kColsInplaceJobs = 16;
 
-void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s) {
-  const Tuning tu = get_tuning(maxN, a.job[0].M, nb);
-  const bool cip = nb >= kColsInplaceJobs && tu.rows_inplace && tu.cols_width == 4;
-  size_t lc = 0;
-  for (int b = 0; b < nb; ++b) lc = std::max(lc, cols_lds(a.job[b].N, a.job[b].M, tu.cols_width, cip));
-  int maxM = 1;
-  for (int b = 0; b < nb; ++b) maxM = std::max(maxM, a.job[b].M);
-  if (nb == 1) {
-    const JobRec& jb = a.job[0];
-    const ColsKernel1 kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, jb.M);
-    (void)ensure_lds((const void*)kc1, lc);
-    launch_k(TK_COLS, kc1, dim3(maxN / tu.cols_width, 1), dim3(256), lc, s, jb.ws, jb.I, t, jb.J, jb.T,
-             jb.N | (jb.M << 16), jb.status);
-    return;
-  }
-  const SweepKernel kc = cols_kernel(tu.cols_radix, tu.cols_width, cip, maxM);
-  (void)ensure_lds((const void*)kc, lc);
-  launch_k(TK_COLS, kc, dim3(maxN / tu.cols_width, nb), dim3(256), lc, s, a, t);
-}
-
 void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_err, dim3(8, nb), dim3(256), 0, s, a);
 }

@@ -33,7 +33,7 @@ struct LaunchArgs {
 
 // Workspace layout of one job; identical on host and device.
 struct WsLayout {
-  size_t psi[2], patch[2], probe1, pmax[2], omax[2], box[2], err, isum, cb, db, total;
+  size_t psi[2], patch[2], probe1, pmax[2], omax[2], err, isum, cb, db, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~size_t(255); }
@@ -54,12 +54,10 @@ __host__ __device__ inline WsLayout ws_layout(int N, int M, int T) {
   MRPIE_TAKE(L.pmax[1], (size_t)N * 4)
   MRPIE_TAKE(L.omax[0], (size_t)N * 4)
   MRPIE_TAKE(L.omax[1], (size_t)N * 4)
-  MRPIE_TAKE(L.box[0], 16)
-  MRPIE_TAKE(L.box[1], 16)
   MRPIE_TAKE(L.err, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)
   MRPIE_TAKE(L.isum, (size_t)(T > 0 ? T : 1) * kErrSlots * 8)  // same slots: sums of max(I, 0)
-  MRPIE_TAKE(L.cb, NN * 8)   // subpixel path: shifted-crop spectra
-  MRPIE_TAKE(L.db, NN * 8)   // subpixel path: object-update spectra
+  MRPIE_TAKE(L.cb, NN * 8)   // subpixel path: crop rows moved along x
+  MRPIE_TAKE(L.db, NN * 8)   // subpixel path: object update moved back along y
 #undef MRPIE_TAKE
   L.total = off;
   return L;
@@ -78,7 +76,7 @@ struct Tuning {
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);
 
-// Subpixel / refining sweep (six launches per position).  `reg_ref`,
+// Subpixel / refining sweep (four launches per position).  `reg_ref`,
 // `reg_mov` ([J][N][N] each) receive the patch before and after its update
 // when `record` is set.
 struct SubpixelExtra {
@@ -99,10 +97,9 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
 
 // Launch helpers shared by the sweep drivers: clear the per-iteration error
 // partials; finish (copy the probe back from the workspace buffer when
-// `probe_back`, sum the intensities, write err_out); one column pass.
+// `probe_back`, sum the intensities, write err_out).
 void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s);
 void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream_t s, bool probe_back = true);
-void launch_cols_pass(const LaunchArgs& a, int maxN, int nb, int t, hipStream_t s);
 
 // One-workgroup sweep of jobs whose M modes of N x N fit the LDS together
 // (M N^2 <= 16384); every job of `jobs` must fit.

@@ -4,25 +4,28 @@
 //
 // A position at pos = n + f (n = floor(pos + 0.5)) is cropped at n and moved
 // by the fraction f with a band-limited Fourier phase ramp, o = S_f(crop);
-// the object update is moved back, O[box] += S_{-f}(delta_o).  Each Fourier
-// move costs one 2-D FFT round trip, so a position takes six launches
-// (R = row pass over probe rows, C = column pass over detector columns):
+// the object update is moved back, O[box] += S_{-f}(delta_o).  The ramp
+// e^{2 pi i (k_y f_y + k_x f_x) / N} factors into one ramp per axis, so the
+// move along x is a row FFT, ramp and inverse row FFT inside a row pass and
+// the move along y the same inside a column pass; both ride on the passes
+// that the exit waves' 2-D FFT needs anyway, and a position takes four
+// launches (R = one workgroup per patch row, C = one per patch column):
 //
-//   k_sp_gather  (R, s-1 -> s)  inverse row FFT of S_{-f} delta_o of step
-//                s-1, object update of the box rows that are rows of box s
-//                or leave it; gather crop rows of box s (merged), row FFT
-//   k_sp_ramp    (C, s)  column FFT, x e^{+2 pi i k.f/N} / N^2, inverse
-//   k_sp_exit    (R, s)  inverse row FFT -> o_s; exit waves P_p o_s, row FFTs
-//   k_cols       (C, s)  modulus replacement (Eq. 7), shared with the
-//                integer-crop sweep
-//   k_sp_update  (R, s)  inverse row FFTs -> psi'; probe update of row r
-//                (Eq. 5); delta_o row r (Eq. 6); row FFT of delta_o
-//   k_sp_ramp    (C, s)  column FFT, x e^{-2 pi i k.f/N} / N^2, inverse
+//   k_sp_rows_gather (R, s-1 -> s)  x back-move of delta_o of step s-1 and
+//                    object update of the box rows that are rows of box s or
+//                    leave it; gather crop rows of box s (merged), x move
+//   k_sp_cols_exit   (C, s)  y move -> o_s; exit waves P_p o_s (Eq. 4);
+//                    column FFTs; maxima of |o|^2 and sum_p |P_p|^2
+//   k_sp_rows_mod    (R, s)  row FFTs, mode-summed modulus replacement
+//                    (Eq. 7), inverse row FFTs
+//   k_sp_cols_update (C, s)  inverse column FFTs -> psi'; probe update (Eq. 5)
+//                    and delta_o (Eq. 6) of column u; y back-move of delta_o
 //
-// With refinement the patch before (o_s) and after (o_s + delta_o) the
-// update are recorded for the registration batch that follows each
-// iteration.  Every workgroup writes only its own rows / columns of each
-// buffer, so the path is deterministic like the integer-crop sweep.
+// A move whose fraction is exactly 0 is skipped (the crop is used as is), so
+// integer positions take no Fourier round trip at all.  With refinement the
+// patch before (o_s) and after (o_s + delta_o) the update are recorded for
+// the registration.  Every workgroup writes only its own rows / columns of
+// each buffer, so the path is deterministic like the integer-crop sweep.
 #include <algorithm>
 #include <cmath>
 
@@ -31,57 +34,75 @@
 
 namespace mrpie {
 
-__device__ __forceinline__ size_t pick2(const size_t (&a)[2], int i) { return i ? a[1] : a[0]; }
-
 struct SpArgs {
-  LaunchArgs la;  // one job (la.job[0])
+  Common c;
+  JobRec jb;
   int subpixel;
   float2* reg_ref;
   float2* reg_mov;
   int record_start;
 };
 
-__device__ __forceinline__ bool recording(const SpArgs& a, const JobRec& jb, int t) {
-  return a.reg_ref && (a.la.c.iter_offset + t / jb.J) >= a.record_start;
+__device__ __forceinline__ bool recording(const SpArgs& a, int t) {
+  return a.reg_ref && (a.c.iter_offset + t / a.jb.J) >= a.record_start;
 }
 
-// ---------------------------------------------------------------- gather
+// Box corner and fraction of position j; the fraction is 0 for a clamped
+// corner and with subpixel moves off.  The positions do not change within a
+// launch sequence (the refining sweep moves them only after its last step of
+// an iteration), so every pass recomputes the boxes it needs.
+__device__ __forceinline__ void box_frac(const SpArgs& a, int j, int N, int* ny, int* nx, float* fy, float* fx,
+                                         int* status) {
+  const JobRec& jb = a.jb;
+  const float py = jb.pos[2 * j], px = jb.pos[2 * j + 1];
+  *ny = box_corner(py, jb.H - N, status);
+  *nx = box_corner(px, jb.W - N, status);
+  float y = 0.f, x = 0.f;
+  if (a.subpixel) {
+    y = py - (float)*ny;
+    x = px - (float)*nx;
+    if (!(y >= -0.5f && y < 0.5f)) y = 0.f;
+    if (!(x >= -0.5f && x < 0.5f)) x = 0.f;
+  }
+  *fy = y;
+  *fx = x;
+}
+
+// e^{sg 2 pi i k f / N} / N for FFT index k (signed frequency in fftfreq
+// order, Nyquist -> -N/2): one axis of the ramp and the 1/N of that axis'
+// unnormalised round trip.
+__device__ __forceinline__ float2 ramp1(int k, float f, float sg, int N) {
+  const int ks = k < N / 2 ? k : k - N;
+  float sn, cs;
+  sincospif(sg * 2.f * (float)ks * f / (float)N, &sn, &cs);
+  const float s = 1.f / (float)N;
+  return make_float2(cs * s, sn * s);
+}
+
+// ---------------------------------------------------------------- R: update + gather
 template <int N>
-__device__ void sp_gather(const SpArgs& a, const JobRec& jb, int t, int mode, float2* smem) {
+__device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
+  const JobRec& jb = a.jb;
   const int r = blockIdx.x;
-  const int total = jb.J * jb.T;
   if (r >= N) return;
   const bool has_prev = mode != 0, has_next = mode != 2;
-  const int cur = t & 1, prv = (t + 1) & 1;
-  const int jn = has_next ? t % jb.J : 0;
-  (void)total;
   const WsLayout L = ws_layout(N, jb.M, jb.T);
   char* ws = jb.ws;
   const int c = threadIdx.x;
   const bool lane = c < N;
   float2* tw = smem;
   float2* orow = tw + N;
-  float2* A = orow + N;       // 2*N
-  float2* B = A + 2 * N;      // 2*N
+  float2* A = orow + N;  // 2N
+  float2* B = A + 2 * N; // 2N
 
-  int ny_n = 0, nx_n = 0;
-  float fy = 0.f, fx = 0.f;
-  if (has_next) {
-    const float py = jb.pos[2 * jn], px = jb.pos[2 * jn + 1];
-    ny_n = box_corner(py, jb.H - N, jb.status);
-    nx_n = box_corner(px, jb.W - N, jb.status);
-    if (a.subpixel) {
-      fy = py - (float)ny_n;
-      fx = px - (float)nx_n;
-      if (!(fy >= -0.5f && fy < 0.5f)) fy = 0.f;  // clamped corner: no move
-      if (!(fx >= -0.5f && fx < 0.5f)) fx = 0.f;
-    }
-  }
-  const int* bp = (const int*)(ws + pick2(L.box, prv));
-  int ny_p = 0, nx_p = 0, rb1 = -1, rb2 = -1;
+  int ny_n = 0, nx_n = 0, ny_p = 0, nx_p = 0;
+  float fy_n = 0.f, fx_n = 0.f, fy_p = 0.f, fx_p = 0.f;
+  if (has_next) box_frac(a, t % jb.J, N, &ny_n, &nx_n, &fy_n, &fx_n, jb.status);
+  if (has_prev) box_frac(a, (t - 1) % jb.J, N, &ny_p, &nx_p, &fy_p, &fx_p, nullptr);
+  // rows of box s-1 this workgroup updates: rb1 = the one that is row r of
+  // box s, rb2 = one that leaves the box
+  int rb1 = -1, rb2 = -1;
   if (has_prev) {
-    ny_p = bp[0];
-    nx_p = bp[1];
     if (has_next) {
       const int dy = ny_n - ny_p;
       if (r + dy >= 0 && r + dy < N) rb1 = r + dy;
@@ -107,31 +128,39 @@ __device__ void sp_gather(const SpArgs& a, const JobRec& jb, int t, int mode, fl
       if (!(rb1 >= 0 && gx >= nx_p && gx < nx_p + N)) og = jb.obj[(size_t)(ny_n + r) * jb.W + gx];
     }
   }
-  if (has_next && r == 0 && c == 0) {
-    int* bc = (int*)(ws + pick2(L.box, cur));
-    bc[0] = ny_n;
-    bc[1] = nx_n;
-    bc[2] = __float_as_int(fy);
-    bc[3] = __float_as_int(fx);
-  }
   load_twiddles<N>(tw);
   if (has_prev) {
-    if (lane) {
-      A[c] = d1;
-      A[N + c] = d2;
+    float2 e1 = d1, e2 = d2;
+    if (fx_p != 0.f) {  // x back-move (db is already moved back along y)
+      if (lane) {
+        A[c] = d1;
+        A[N + c] = d2;
+      }
+      __syncthreads();
+      float2* F = fft_lds<N, false, false>(A, B, 2, tw);
+      float2* G = (F == A) ? B : A;
+      if (lane) {
+        const float2 w = ramp1(c, fx_p, -1.f, N);
+        G[c] = cmul(F[c], w);
+        G[N + c] = cmul(F[N + c], w);
+      }
+      __syncthreads();
+      float2* H = fft_lds<N, true, false>(G, F, 2, tw);
+      if (lane) {
+        e1 = H[c];
+        e2 = H[N + c];
+      }
     }
-    __syncthreads();
-    float2* R = fft_lds<N, true>(A, B, 2, tw);
     bool bad = false;
     if (lane) {
       if (rb1 >= 0) {
-        const float2 on = cadd(o1, R[c]);
+        const float2 on = cadd(o1, e1);
         jb.obj[(size_t)(ny_p + rb1) * jb.W + nx_p + c] = on;
         orow[c] = on;
         bad |= !(isfinite(on.x) && isfinite(on.y));
       }
       if (rb2 >= 0) {
-        const float2 on = cadd(o2, R[N + c]);
+        const float2 on = cadd(o2, e2);
         jb.obj[(size_t)(ny_p + rb2) * jb.W + nx_p + c] = on;
         bad |= !(isfinite(on.x) && isfinite(on.y));
       }
@@ -140,163 +169,213 @@ __device__ void sp_gather(const SpArgs& a, const JobRec& jb, int t, int mode, fl
     __syncthreads();
   }
   if (!has_next) return;
+  // crop row r of box s (the part inside box s-1 taken from the row just
+  // updated), x move
+  float2 v = make_float2(0.f, 0.f);
   if (lane) {
-    const int gx = nx_n + c;
-    A[c] = (rb1 >= 0 && gx >= nx_p && gx < nx_p + N) ? orow[gx - nx_p] : og;
+    // (a value select on an in-range read: no pointer select over address spaces)
+    const int xo = nx_n + c - nx_p;
+    const float2 ov = orow[min(max(xo, 0), N - 1)];
+    v = (rb1 >= 0 && xo >= 0 && xo < N) ? ov : og;
   }
-  __syncthreads();
-  float2* R = fft_lds<N, false>(A, B, 1, tw);
-  float2* cb = (float2*)(ws + L.cb);
-  if (lane) cb[(size_t)r * N + c] = R[c];
+  if (fx_n != 0.f) {
+    if (lane) A[c] = v;
+    __syncthreads();
+    float2* F = fft_lds<N, false, false>(A, B, 1, tw);
+    float2* G = (F == A) ? B : A;
+    if (lane) G[c] = cmul(F[c], ramp1(c, fx_n, 1.f, N));
+    __syncthreads();
+    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    if (lane) v = H[c];
+  }
+  if (lane) ((float2*)(ws + L.cb))[(size_t)r * N + c] = v;
 }
 
-// ---------------------------------------------------------------- ramp
-// Column pass of the Fourier move: column FFT of buffer `which` (0 = crop
-// spectra, +f; 1 = update spectra, -f), phase ramp and the 1/N^2 of the
-// unnormalised 2-D round trip, inverse column FFT, in place.
+// ---------------------------------------------------------------- C: exit waves
 template <int N>
-__device__ void sp_ramp(const SpArgs& a, const JobRec& jb, int t, int which, float2* smem) {
+__device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const JobRec& jb = a.jb;
   const int u = xcd_unit(blockIdx.x, gridDim.x);
   if (u >= N || t >= jb.J * jb.T) return;
-  const WsLayout L = ws_layout(N, jb.M, jb.T);
+  const int M = jb.M, jn = t % jb.J;
+  const WsLayout L = ws_layout(N, M, jb.T);
   char* ws = jb.ws;
-  float2* buf = (float2*)(ws + (which == 0 ? L.cb : L.db));
-  const int* bc = (const int*)(ws + pick2(L.box, t & 1));
-  const float fy = __int_as_float(bc[2]), fx = __int_as_float(bc[3]);
-  const float sg = which == 0 ? 1.f : -1.f;
+  const size_t NN = (size_t)N * N;
   const int k = threadIdx.x;
   const bool lane = k < N;
   float2* tw = smem;
-  float2* A = tw + N;
-  float2* B = A + N;
+  float2* A = tw + N;     // M N
+  float2* B = A + M * N;  // M N
+  __shared__ float redf[32];
+  int ny, nx;
+  float fy, fx;
+  box_frac(a, jn, N, &ny, &nx, &fy, &fx, nullptr);
+  const float2* Pc = (t & 1) == 0 ? jb.probe : (const float2*)(ws + L.probe1);
   float2 v = make_float2(0.f, 0.f);
-  if (lane) v = buf[(size_t)k * N + u];
-  load_twiddles<N>(tw);
-  if (lane) A[k] = v;
-  __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, 1, tw);
-  float2* G = (F == A) ? B : A;
-  if (lane) {
-    const int ky = k < N / 2 ? k : k - N;   // fftfreq order, Nyquist -> -N/2
-    const int kx = u < N / 2 ? u : u - N;
-    float sn, cs;
-    sincospif(sg * 2.f * ((float)ky * fy + (float)kx * fx) / (float)N, &sn, &cs);
-    const float s2 = 1.f / ((float)N * (float)N);
-    G[k] = cscale(cmul(F[k], make_float2(cs, sn)), s2);
-  }
-  __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, 1, tw);
-  if (lane) buf[(size_t)k * N + u] = H[k];
-}
-
-// ---------------------------------------------------------------- exit waves
-template <int N>
-__device__ void sp_exit(const SpArgs& a, const JobRec& jb, int t, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES;
-  const int r = blockIdx.x;
-  if (r >= N || t >= jb.J * jb.T) return;
-  const int M = jb.M;
-  const int cur = t & 1, jn = t % jb.J;
-  const WsLayout L = ws_layout(N, M, jb.T);
-  char* ws = jb.ws;
-  const size_t NN = (size_t)N * N;
-  const int c = threadIdx.x;
-  const bool lane = c < N;
-  float2* tw = smem;
-  float2* A = tw + N;          // (M+1)*N
-  float2* B = A + (M + 1) * N; // (M+1)*N
-  __shared__ float redf[16];
-  const float2* Pc = cur == 0 ? jb.probe : (const float2*)(ws + L.probe1);
-  float2 cbv = make_float2(0.f, 0.f);
   float2 P[MM];
   if (lane) {
-    cbv = ((const float2*)(ws + L.cb))[(size_t)r * N + c];
+    v = ((const float2*)(ws + L.cb))[(size_t)k * N + u];
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) P[p] = Pc[p * NN + (size_t)r * N + c];
+      if (p < M) P[p] = Pc[p * NN + (size_t)k * N + u];
   }
   load_twiddles<N>(tw);
-  if (lane) A[c] = cbv;
-  __syncthreads();
-  float2* R = fft_lds<N, true>(A, B, 1, tw);
-  float2* W = (R == A) ? B : A;
+  float2 o = v;
+  if (fy != 0.f) {  // y move
+    if (lane) A[k] = v;
+    __syncthreads();
+    float2* F = fft_lds<N, false, false>(A, B, 1, tw);
+    float2* G = (F == A) ? B : A;
+    if (lane) G[k] = cmul(F[k], ramp1(k, fy, 1.f, N));
+    __syncthreads();
+    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    if (lane) o = H[k];
+    __syncthreads();
+  }
   float om = 0.f, pm = 0.f;
   if (lane) {
-    const float2 o = R[c];
-    ((float2*)(ws + pick2(L.patch, cur)))[(size_t)r * N + c] = o;
-    if (recording(a, jb, t)) a.reg_ref[((size_t)jn * N + r) * N + c] = o;
+    ((float2*)(ws + L.patch[0]))[(size_t)k * N + u] = o;
+    if (recording(a, t)) a.reg_ref[((size_t)jn * N + k) * N + u] = o;
     om = cabs2(o);
-    float ps = 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) {
-        ps += cabs2(P[p]);
-        W[p * N + c] = cmul(P[p], o);
+        pm += cabs2(P[p]);
+        A[p * N + k] = cmul(P[p], o);
       }
-    pm = ps;
   }
-  om = block_max(om, redf);
-  pm = block_max(pm, redf + 8);
+  block_max2(om, pm, redf, om, pm);  // (its barriers also publish A)
   if (threadIdx.x == 0) {
-    ((float*)(ws + pick2(L.omax, cur)))[r] = om;
-    ((float*)(ws + pick2(L.pmax, cur)))[r] = pm;
+    ((float*)(ws + L.omax[0]))[u] = om;
+    ((float*)(ws + L.pmax[0]))[u] = pm;
   }
-  float2* S = fft_lds<N, false>(W, R, M, tw);
-  float2* dst = (float2*)(ws + pick2(L.psi, cur));
-  for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
-    const int p = i / N, cc = i - p * N;
-    dst[p * NN + (size_t)r * N + cc] = S[i];
+  float2* S = fft_lds<N, false, false>(A, B, M, tw);
+  float2* psi = (float2*)(ws + L.psi[0]);
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) psi[p * NN + (size_t)k * N + u] = S[p * N + k];
   }
 }
 
-// ---------------------------------------------------------------- updates
+// ---------------------------------------------------------------- R: modulus
 template <int N>
-__device__ void sp_update(const SpArgs& a, const JobRec& jb, int t, float2* smem) {
+__device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
   constexpr int MM = MRPIE_MAX_MODES;
+  const JobRec& jb = a.jb;
   const int r = blockIdx.x;
   if (r >= N || t >= jb.J * jb.T) return;
-  const int M = jb.M;
-  const int cur = t & 1, nxt = (t + 1) & 1, jn = t % jb.J;
-  const Common& cm = a.la.c;
+  const int M = jb.M, it = t / jb.J, jn = t - it * jb.J;
   const WsLayout L = ws_layout(N, M, jb.T);
   char* ws = jb.ws;
   const size_t NN = (size_t)N * N;
   const int c = threadIdx.x;
   const bool lane = c < N;
   float2* tw = smem;
-  float2* A = tw + N;      // M*N
-  float2* B = A + M * N;   // M*N
-  __shared__ float redf[16];
-  const float2* Pold = cur == 0 ? jb.probe : (const float2*)(ws + L.probe1);
-  float2* Pnew = nxt == 0 ? jb.probe : (float2*)(ws + L.probe1);
-  const float2* psi = (const float2*)(ws + pick2(L.psi, cur));
-  float2 pv[MM], P[MM];
+  float2* A = tw + N;     // M N
+  float2* B = A + M * N;  // M N
+  float2* psi = (float2*)(ws + L.psi[0]);
+  // per-wave partials of the Fourier error and of the intensity sum
+  const size_t slot = (size_t)it * kErrSlots + r * 4 + (c >> 6);
+  double* err_slot = (double*)(ws + L.err) + slot;
+  double* isum_slot = (double*)(ws + L.isum) + slot;
+  const double err_old = (c & 63) == 0 ? *err_slot : 0.0;
+  const double isum_old = (c & 63) == 0 ? *isum_slot : 0.0;
+  float Iv = 0.f;
+  if (lane) {
+    Iv = jb.I[(size_t)jn * NN + (size_t)r * N + c];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) A[p * N + c] = psi[p * NN + (size_t)r * N + c];
+  }
+  load_twiddles<N>(tw);
+  __syncthreads();
+  float2* F = fft_lds<N, false, false>(A, B, M, tw);
+  float2* G = (F == A) ? B : A;
+  // Eq. 7: the 2-D transform is unnormalised (N x unitary) and so is the
+  // inverse, so the scale factor carries one 1/N
+  double e = 0.0, isv = 0.0;
+  if (lane) {
+    const float invN = 1.0f / (float)N;
+    float S = 0.f;
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) S += cabs2(F[p * N + c]);
+    const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+    const float Au = S * rs;
+    const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv, 0.f));
+    const float d = Au * invN - sq;
+    e = (double)d * (double)d;
+    isv = (double)fmaxf(Iv, 0.f);
+    if (!isfinite(S)) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
+    const float f = sq * rs * invN;
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) G[p * N + c] = cscale(F[p * N + c], f);
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true, false>(G, F, M, tw);
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) psi[p * NN + (size_t)r * N + c] = H[p * N + c];
+  }
+  e = wave_sum(e);
+  isv = wave_sum(isv);
+  if ((c & 63) == 0) {
+    *err_slot = err_old + e;
+    *isum_slot = isum_old + isv;
+  }
+}
+
+// ---------------------------------------------------------------- C: updates
+template <int N>
+__device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
+  constexpr int MM = MRPIE_MAX_MODES;
+  const JobRec& jb = a.jb;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  if (u >= N || t >= jb.J * jb.T) return;
+  const int M = jb.M, jn = t % jb.J;
+  const Common& cm = a.c;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  char* ws = jb.ws;
+  const size_t NN = (size_t)N * N;
+  const int k = threadIdx.x;
+  const bool lane = k < N;
+  float2* tw = smem;
+  float2* A = tw + N;     // M N
+  float2* B = A + M * N;  // M N
+  __shared__ float redf[32];
+  int ny, nx;
+  float fy, fx;
+  box_frac(a, jn, N, &ny, &nx, &fy, &fx, nullptr);
+  const float2* Pold = (t & 1) == 0 ? jb.probe : (const float2*)(ws + L.probe1);
+  float2* Pnew = (t & 1) == 0 ? (float2*)(ws + L.probe1) : jb.probe;
+  const float2* psi = (const float2*)(ws + L.psi[0]);
+  float2 P[MM];
   float2 o = make_float2(0.f, 0.f);
   float om_in = 0.f, pm_in = 0.f;
   if (lane) {
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) {
-        pv[p] = psi[p * NN + (size_t)r * N + c];
-        P[p] = Pold[p * NN + (size_t)r * N + c];
+        A[p * N + k] = psi[p * NN + (size_t)k * N + u];
+        P[p] = Pold[p * NN + (size_t)k * N + u];
       }
-    o = ((const float2*)(ws + pick2(L.patch, cur)))[(size_t)r * N + c];
-    om_in = ((const float*)(ws + pick2(L.omax, cur)))[c];
-    pm_in = ((const float*)(ws + pick2(L.pmax, cur)))[c];
+    o = ((const float2*)(ws + L.patch[0]))[(size_t)k * N + u];
+    om_in = ((const float*)(ws + L.omax[0]))[k];
+    pm_in = ((const float*)(ws + L.pmax[0]))[k];
   }
   load_twiddles<N>(tw);
-  if (lane) {
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) A[p * N + c] = pv[p];
-  }
-  const float omax = block_max(om_in, redf);
-  const float pmaxv = block_max(pm_in, redf + 8);
-  float2* R = fft_lds<N, true>(A, B, M, tw);
+  float omax, pmaxv;
+  block_max2(om_in, pm_in, redf, omax, pmaxv);  // (its barriers also publish A)
+  float2* R = fft_lds<N, true, false>(A, B, M, tw);
   float2* W = (R == A) ? B : A;
   const int it_abs = cm.iter_offset + t / jb.J;
   const bool upd_p = it_abs >= cm.probe_update_start;
   bool bad = false;
+  float2 dlt = make_float2(0.f, 0.f);
   if (lane) {
     const float o2 = cabs2(o);
     const float dP = cm.beta * omax + (1.f - cm.beta) * o2;
@@ -306,57 +385,58 @@ __device__ void sp_update(const SpArgs& a, const JobRec& jb, int t, float2* smem
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) {
-        const float2 d = csub(R[p * N + c], cmul(P[p], o));
+        const float2 d = csub(R[p * N + k], cmul(P[p], o));
         num = cadd(num, cmulc(d, P[p]));
         Ps += cabs2(P[p]);
         const float2 Pn = cadd(P[p], cscale(cmulc(d, o), gp));
-        Pnew[p * NN + (size_t)r * N + c] = Pn;
+        Pnew[p * NN + (size_t)k * N + u] = Pn;
         bad |= !(isfinite(Pn.x) && isfinite(Pn.y));
       }
     const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
     const float go = dO != 0.f ? cm.alpha_obj / dO : 0.f;
-    const float2 dlt = cscale(num, go);
-    if (recording(a, jb, t)) a.reg_mov[((size_t)jn * N + r) * N + c] = cadd(o, dlt);
-    W[c] = dlt;
+    dlt = cscale(num, go);
+    if (recording(a, t)) a.reg_mov[((size_t)jn * N + k) * N + u] = cadd(o, dlt);
   }
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
-  __syncthreads();
-  float2* S = fft_lds<N, false>(W, R, 1, tw);
-  if (lane) ((float2*)(ws + L.db))[(size_t)r * N + c] = S[c];
+  if (fy != 0.f) {  // y back-move of delta_o
+    if (lane) W[k] = dlt;
+    __syncthreads();
+    float2* F = fft_lds<N, false, false>(W, R, 1, tw);
+    float2* G = (F == W) ? R : W;
+    if (lane) G[k] = cmul(F[k], ramp1(k, fy, -1.f, N));
+    __syncthreads();
+    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    if (lane) dlt = H[k];
+  }
+  if (lane) ((float2*)(ws + L.db))[(size_t)k * N + u] = dlt;
 }
 
 // ---------------------------------------------------------------- kernels
-#define MRPIE_DISPATCH(FN, ...)                         \
-  switch (jb.N) {                                       \
-    case 32: FN<32>(__VA_ARGS__); break;                \
-    case 64: FN<64>(__VA_ARGS__); break;                \
-    case 128: FN<128>(__VA_ARGS__); break;              \
-    case 192: FN<192>(__VA_ARGS__); break;              \
-    default: FN<256>(__VA_ARGS__); break;               \
+#define MRPIE_DISPATCH(FN, ...)              \
+  switch (a.jb.N) {                          \
+    case 32: FN<32>(__VA_ARGS__); break;     \
+    case 64: FN<64>(__VA_ARGS__); break;     \
+    case 128: FN<128>(__VA_ARGS__); break;   \
+    case 192: FN<192>(__VA_ARGS__); break;   \
+    default: FN<256>(__VA_ARGS__); break;    \
   }
 
-__global__ __launch_bounds__(256) void k_sp_gather(const SpArgs a, int t, int mode) {
+__global__ __launch_bounds__(256) void k_sp_rows_gather(const SpArgs a, int t, int mode) {
   extern __shared__ float2 smem[];
-  const JobRec& jb = a.la.job[0];
-  MRPIE_DISPATCH(sp_gather, a, jb, t, mode, smem)
+  MRPIE_DISPATCH(sp_rows_gather, a, t, mode, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_ramp(const SpArgs a, int t, int which) {
+__global__ __launch_bounds__(256) void k_sp_cols_exit(const SpArgs a, int t) {
   extern __shared__ float2 smem[];
-  const JobRec& jb = a.la.job[0];
-  MRPIE_DISPATCH(sp_ramp, a, jb, t, which, smem)
+  MRPIE_DISPATCH(sp_cols_exit, a, t, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_exit(const SpArgs a, int t) {
+__global__ __launch_bounds__(256) void k_sp_rows_mod(const SpArgs a, int t) {
   extern __shared__ float2 smem[];
-  const JobRec& jb = a.la.job[0];
-  MRPIE_DISPATCH(sp_exit, a, jb, t, smem)
+  MRPIE_DISPATCH(sp_rows_mod, a, t, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_update(const SpArgs a, int t) {
+__global__ __launch_bounds__(256) void k_sp_cols_update(const SpArgs a, int t) {
   extern __shared__ float2 smem[];
-  const JobRec& jb = a.la.job[0];
-  MRPIE_DISPATCH(sp_update, a, jb, t, smem)
+  MRPIE_DISPATCH(sp_cols_update, a, t, smem)
 }
-
-// the modulus column pass of the integer-crop sweep (sweep.hip)
 
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s) {
@@ -368,30 +448,26 @@ int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelEx
   int rc = launch_init_twiddles(s);
   if (rc) return rc;
   SpArgs a{};
-  a.la.c = c;
-  a.la.njobs = 1;
-  a.la.job[0] = jb;
+  a.c = c;
+  a.jb = jb;
   a.subpixel = ex.subpixel;
   a.reg_ref = ex.reg_ref;
   a.reg_mov = ex.reg_mov;
   a.record_start = ex.record_start;
   const int N = jb.N, M = jb.M;
   const size_t lg = (size_t)(N + N + 4 * N) * 8;
-  const size_t le = (size_t)(N + 2 * (M + 1) * N) * 8;
-  const size_t lu = (size_t)(N + 2 * M * N) * 8;
-  const size_t lr = (size_t)(N + 2 * N) * 8;
-  MRPIE_HIP(ensure_lds((const void*)k_sp_exit, le));
-  MRPIE_HIP(ensure_lds((const void*)k_sp_update, lu));
+  const size_t lm = (size_t)(N + 2 * M * N) * 8;
+  MRPIE_HIP(ensure_lds((const void*)k_sp_cols_exit, lm));
+  MRPIE_HIP(ensure_lds((const void*)k_sp_rows_mod, lm));
+  MRPIE_HIP(ensure_lds((const void*)k_sp_cols_update, lm));
   const dim3 g(N), blk(256);
   for (int t = t0; t < t1; ++t) {
-    hipLaunchKernelGGL(k_sp_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
-    hipLaunchKernelGGL(k_sp_ramp, g, blk, lr, s, a, t, 0);
-    hipLaunchKernelGGL(k_sp_exit, g, blk, le, s, a, t);
-    launch_cols_pass(a.la, N, 1, t, s);
-    hipLaunchKernelGGL(k_sp_update, g, blk, lu, s, a, t);
-    hipLaunchKernelGGL(k_sp_ramp, g, blk, lr, s, a, t, 1);
+    hipLaunchKernelGGL(k_sp_rows_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
+    hipLaunchKernelGGL(k_sp_cols_exit, g, blk, lm, s, a, t);
+    hipLaunchKernelGGL(k_sp_rows_mod, g, blk, lm, s, a, t);
+    hipLaunchKernelGGL(k_sp_cols_update, g, blk, lm, s, a, t);
   }
-  if (tail) hipLaunchKernelGGL(k_sp_gather, g, blk, lg, s, a, t1, 2);
+  if (tail) hipLaunchKernelGGL(k_sp_rows_gather, g, blk, lg, s, a, t1, 2);
   MRPIE_HIP(hipGetLastError());
   return MRPIE_OK;
 }
