@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "120ffc439f1502742699d39ee8509f22e34989a26b468a47a483bb915801a121",
+    "sha256": "2fca1a4a48e01a3bcfc2777202e944b0b65d3d176e6d10422ce4bbb9b460a9f0",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    "k_rows": {"fetch_kib": 3460.0, "write_kib": 4097.6},
-    "k_cols": {"fetch_kib": 1005.0, "write_kib": 1552.0},
+    "k_rows": {"fetch_kib": 3455.5, "write_kib": 4097.6},
+    "k_cols": {"fetch_kib": 1005.5, "write_kib": 1552.0},
 }
 
 
