@@ -39,13 +39,21 @@ struct ArgMax {
   long long i;
 };
 
-// workgroup argmax with the first-maximum rule (all threads get the result)
-__device__ __forceinline__ ArgMax block_argmax(double v, long long i, double* rv, long long* ri) {
+// first-maximum argmax over one wave (all lanes get the result)
+__device__ __forceinline__ ArgMax wave_argmax(double v, long long i) {
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(v, o, 64);
     const long long oi = __shfl_xor(i, o, 64);
     if (better(ov, oi, v, i)) { v = ov; i = oi; }
   }
+  return ArgMax{v, i};
+}
+
+// workgroup argmax with the first-maximum rule (all threads get the result)
+__device__ __forceinline__ ArgMax block_argmax(double v, long long i, double* rv, long long* ri) {
+  const ArgMax wm = wave_argmax(v, i);
+  v = wm.v;
+  i = wm.i;
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) { rv[w] = v; ri[w] = i; }
@@ -57,21 +65,25 @@ __device__ __forceinline__ ArgMax block_argmax(double v, long long i, double* rv
 }
 
 // ---------------------------------------------------------------- FFT passes
+// Row passes take kRegRW rows per workgroup (one wave per row at N = 256),
+// so every thread of the workgroup has a butterfly in every radix-4 stage.
+constexpr int kRegRW = 4;
+
 template <int N>
 __global__ __launch_bounds__(256) void k_reg_rows(const RegArgs a) {
   __shared__ double2 tw[N];
-  __shared__ double2 A[N], B[N];
-  const int r = blockIdx.x, b = blockIdx.y, which = blockIdx.z;
-  const float2* src = (which == 0 ? a.ref : a.mov) + ((size_t)b * N + r) * N;
+  __shared__ double2 A[kRegRW * N], B[kRegRW * N];
+  const int r0 = blockIdx.x * kRegRW, b = blockIdx.y, which = blockIdx.z;
+  const float2* src = (which == 0 ? a.ref : a.mov) + ((size_t)b * N + r0) * N;
   load_twiddles<N>(tw);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+  for (int i = threadIdx.x; i < kRegRW * N; i += blockDim.x) {
     const float2 v = src[i];
     A[i] = make_double2((double)v.x, (double)v.y);
   }
   __syncthreads();
-  double2* R = fft_lds<N, false>(A, B, 1, tw);
-  double2* dst = a.work + (((size_t)b * 2 + which) * N + r) * N;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = R[i];
+  double2* R = fft_lds<N, false>(A, B, kRegRW, tw);
+  double2* dst = a.work + (((size_t)b * 2 + which) * N + r0) * N;
+  for (int i = threadIdx.x; i < kRegRW * N; i += blockDim.x) dst[i] = R[i];
 }
 
 // CW adjacent columns per workgroup, so every access moves CW * 16
@@ -124,27 +136,28 @@ __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
   }
 }
 
+// kRegRW rows per workgroup; wave w scans row r0 + w of the inverse
+// transform for its first maximum (requires 64 kRegRW threads).
 template <int N>
 __global__ __launch_bounds__(256) void k_reg_coarse(const RegArgs a) {
   __shared__ double2 tw[N];
-  __shared__ double2 A[N], B[N];
-  __shared__ double rv[16];
-  __shared__ long long ri[16];
-  const int r = blockIdx.x, b = blockIdx.y;
-  const double2* src = a.work + ((size_t)b * 2 * N + r) * N;
+  __shared__ double2 A[kRegRW * N], B[kRegRW * N];
+  const int r0 = blockIdx.x * kRegRW, b = blockIdx.y;
+  const double2* src = a.work + ((size_t)b * 2 * N + r0) * N;
   load_twiddles<N>(tw);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) A[i] = src[i];
+  for (int i = threadIdx.x; i < kRegRW * N; i += blockDim.x) A[i] = src[i];
   __syncthreads();
-  double2* R = fft_lds<N, true>(A, B, 1, tw);
+  double2* R = fft_lds<N, true>(A, B, kRegRW, tw);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, r = r0 + w;
   double v = -1.0;
   long long idx = (long long)r * N + N;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    const double m = cabs2(R[i]);
+  for (int i = lane; i < N; i += 64) {
+    const double m = cabs2(R[w * N + i]);
     const long long ii = (long long)r * N + i;
     if (better(m, ii, v, idx)) { v = m; idx = ii; }
   }
-  const ArgMax m = block_argmax(v, idx, rv, ri);
-  if (threadIdx.x == 0) {
+  const ArgMax m = wave_argmax(v, idx);
+  if (lane == 0) {
     a.rowmax_v[(size_t)b * N + r] = m.v;
     a.rowmax_i[(size_t)b * N + r] = m.i;
   }
@@ -191,6 +204,7 @@ template <int N>
 __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
   __shared__ double2 Ks[G1_TU][G1_KC + 1];
   __shared__ double2 Xs[G1_KC][G1_TX + 1];
+  __shared__ double2 tw[N];  // exp(-2 pi i e / N): the lag phase is an N-th root of unity
   const int b = blockIdx.z;
   const int u0 = blockIdx.y * G1_TU, x0 = blockIdx.x * G1_TX;
   const int U = a.U;
@@ -202,6 +216,8 @@ __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  load_twiddles<N>(tw);
+  __syncthreads();
   for (int k0 = 0; k0 < N; k0 += G1_KC) {
     for (int i = threadIdx.x; i < G1_TU * G1_KC; i += blockDim.x) {
       const int uu = i / G1_KC, kk = i - uu * G1_KC;
@@ -213,10 +229,10 @@ __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
       const int ky = k0 + kk, kx = x0 + xx;
       if (kx >= N) { Xs[kk][xx] = make_double2(0.0, 0.0); continue; }
       const double2 x = X[(size_t)ky * N + kx];
-      const double ph = 2.0 * (double)(signed_freq(ky, N) * s0y + signed_freq(kx, N) * s0x) / (double)N;
-      double s, c;
-      sincospi(ph, &s, &c);
-      Xs[kk][xx] = cmul(x, make_double2(c, s));
+      // e^{2 pi i e / N} with e = (ky s0y + kx s0x) mod N = conj(tw[e])
+      int e = (signed_freq(ky, N) * s0y + signed_freq(kx, N) * s0x) % N;
+      e += e < 0 ? N : 0;
+      Xs[kk][xx] = cmulc(x, tw[e]);
     }
     __syncthreads();
 #pragma unroll 4
@@ -410,9 +426,9 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
     a.mov = mov + (size_t)b0 * N * N;
     a.shift = shift + 2 * (size_t)b0;
     a.peak = peak + 4 * (size_t)b0;
-    hipLaunchKernelGGL(k_reg_rows<N>, dim3(N, nb, 2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reg_rows<N>, dim3(N / kRegRW, nb, 2), dim3(256), 0, s, a);
     launch_k(TK_REG, k_reg_cols<N>, dim3(N / kRegCW, nb), dim3(256), reg_cols_lds(N), s, a);
-    hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N, nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N / kRegRW, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_s0, dim3(nb), dim3(256), 0, s, a, N);
     launch_k(TK_GEMM, k_reg_gemm1<N>, dim3((N + G1_TX - 1) / G1_TX, (U + G1_TU - 1) / G1_TU, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_gemm2<N>, dim3(gt, gt, nb), dim3(256), 0, s, a);
