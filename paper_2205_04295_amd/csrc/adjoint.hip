@@ -44,7 +44,7 @@ __device__ void adj_p1(const AdjArgs& a, float2* smem) {
   load_twiddles<N>(tw);
   if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, false>(A, B, 1, tw);
+  float2* R = fft_lds<N, false, false>(A, B, 1, tw);
   if (c < N) a.Cp[chunk_off(b, N) + (size_t)r * N + c] = R[c];
 }
 
@@ -103,7 +103,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
     A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false>(A, B, CW, tw);
   float2* G = (F == A) ? B : A;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -115,7 +115,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
     G[c * N + k] = cscale(fo, 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, CW, tw);
+  float2* H = fft_lds<N, true, false>(G, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -145,7 +145,7 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
   load_twiddles<N>(tw);
   if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, true>(A, B, 1, tw);
+  float2* R = fft_lds<N, true, false>(A, B, 1, tw);
   float2* W = (R == A) ? B : A;
   if (c < N) {
     const float2 o = R[c];
@@ -155,7 +155,7 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
       if (p < M) W[p * N + c] = cmul(P[p], o);
   }
   __syncthreads();
-  float2* S = fft_lds<N, false>(W, R, M, tw);
+  float2* S = fft_lds<N, false, false>(W, R, M, tw);
   float2* psi = a.Psi + (size_t)b * M * NN;
   for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
     const int p = i / N, cc = i - p * N;
@@ -164,16 +164,18 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
 }
 
 // P4 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
-template <int N>
+// IP: in-place transforms (one M CW N buffer instead of two, so more
+// workgroups share a CU; used while the register arrays it needs stay small)
+template <int N, int MM, bool IP>
 __device__ void adj_p4(const AdjArgs& a, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES, CW = kAdjCWM, PIX = (N * CW + 255) / 256;
+  constexpr int CW = kAdjCWM, PIX = (N * CW + 255) / 256;
   const int u = col_group(gridDim.x), b = blockIdx.y, M = a.M;
   if (u >= N / CW) return;
   const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
   float2* A = tw + N;          // transform (p, c) at (p * CW + c) * N
-  float2* B = A + M * CW * N;
+  float2* B = IP ? A : A + M * CW * N;
   __shared__ double redd[16];
   float2* psi = a.Psi + (size_t)b * M * NN;
   const float* Ij = a.I + (size_t)j * NN;
@@ -188,8 +190,14 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
   }
   load_twiddles<N>(tw);
   __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, M * CW, tw);
-  float2* G = (F == A) ? B : A;
+  float2* F;
+  if constexpr (IP) {
+    fft_lds_inplace<N, false, false, MM * CW, 256>(A, M * CW, tw);
+    F = A;
+  } else {
+    F = fft_lds<N, false, false>(A, B, M * CW, tw);
+  }
+  float2* G = IP ? F : ((F == A) ? B : A);  // (in place: each thread rescales the pixels it reads)
   double e = 0.0;
   const float invN = 1.f / (float)N;
 #pragma unroll
@@ -200,19 +208,27 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) S += cabs2(F[(p * CW + c) * N + k]);
-    const float Au = sqrtf(S);
-    const float sq = sqrtf(fmaxf(Ij[(size_t)k * N + u0 + c], 0.f));
+    // hardware reciprocal square root and square root (about 1 ulp)
+    const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+    const float Au = S * rs;
+    const float sq = __builtin_amdgcn_sqrtf(fmaxf(Ij[(size_t)k * N + u0 + c], 0.f));
     const float d = Au * invN - sq;
     e += (double)d * (double)d;
     // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
     // inverse 2-D transform
-    const float wgt = Au > 0.f ? (1.f - sq * (float)N / Au) * invN * invN : 0.f;
+    const float wgt = S > 0.f ? (1.f - sq * (float)N * rs) * invN * invN : 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) G[(p * CW + c) * N + k] = cscale(F[(p * CW + c) * N + k], wgt);
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G, F, M * CW, tw);
+  const float2* H;
+  if constexpr (IP) {
+    fft_lds_inplace<N, true, false, MM * CW, 256>(G, M * CW, tw);
+    H = G;
+  } else {
+    H = fft_lds<N, true, false>(G, F, M * CW, tw);
+  }
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -262,7 +278,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
         if (p < M) A[p * N + c] = psi[p * NN + roff];
     }
     __syncthreads();
-    float2* R = fft_lds<N, true>(A, B, M, tw);
+    float2* R = fft_lds<N, true, false>(A, B, M, tw);
     float2* W = (R == A) ? B : A;
     if (c < N) {
       float2 g = make_float2(0.f, 0.f);
@@ -276,7 +292,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
       W[c] = cscale(g, 2.f);
     }
     __syncthreads();
-    float2* S = fft_lds<N, false>(W, R, 1, tw);
+    float2* S = fft_lds<N, false, false>(W, R, 1, tw);
     if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
     __syncthreads();  // A, B are reused by the next position
   }
@@ -318,7 +334,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false>(A, B, CW, tw);
   float2* G2 = (F == A) ? B : A;
   double gy = 0.0, gx = 0.0;
 #pragma unroll
@@ -336,7 +352,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     G2[c * N + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true>(G2, F, CW, tw);
+  float2* H = fft_lds<N, true, false>(G2, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -366,7 +382,7 @@ __device__ void adj_p7(const AdjArgs& a, float2* smem) {
   load_twiddles<N>(tw);
   if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, true>(A, B, 1, tw);
+  float2* R = fft_lds<N, true, false>(A, B, 1, tw);
   if (c < N) g[(size_t)r * N + c] = R[c];
 }
 
@@ -384,7 +400,20 @@ __device__ void adj_p7(const AdjArgs& a, float2* smem) {
 MRPIE_ADJ_KERNEL(k_adj_p1, adj_p1)
 MRPIE_ADJ_KERNEL(k_adj_p2, adj_p2)
 MRPIE_ADJ_KERNEL(k_adj_p3, adj_p3)
-MRPIE_ADJ_KERNEL(k_adj_p4, adj_p4)
+// the mode pass per bound MM >= M on the modes (register arrays of the
+// in-place transforms)
+template <int MM>
+__global__ __launch_bounds__(256) void k_adj_p4(const AdjArgs a) {
+  constexpr bool IP = MM <= 4;
+  extern __shared__ float2 smem[];
+  switch (a.N) {
+    case 32: adj_p4<32, MM, IP>(a, smem); break;
+    case 64: adj_p4<64, MM, IP>(a, smem); break;
+    case 128: adj_p4<128, MM, IP>(a, smem); break;
+    case 192: adj_p4<192, MM, IP>(a, smem); break;
+    default: adj_p4<256, MM, IP>(a, smem); break;
+  }
+}
 MRPIE_ADJ_KERNEL(k_adj_p5, adj_p5)
 MRPIE_ADJ_KERNEL(k_adj_p6, adj_p6)
 MRPIE_ADJ_KERNEL(k_adj_p7, adj_p7)
@@ -534,12 +563,13 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   // LDS of the row passes (one / M+1 / M transforms), of the single-field
   // column passes (kAdjCW1 transforms) and of the mode column pass
   const size_t l1 = (size_t)3 * N * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
-  const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * N) * 8, lcm = (size_t)(N + 2 * M * kAdjCWM * N) * 8;
+  const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * N) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * N) * 8;
   MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p2, lc1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p6, lc1));
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p4, lcm));
+  const auto kp4 = M <= 1 ? k_adj_p4<1> : M <= 2 ? k_adj_p4<2> : M <= 4 ? k_adj_p4<4> : k_adj_p4<MRPIE_MAX_MODES>;
+  MRPIE_HIP(ensure_lds((const void*)kp4, lcm));
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
@@ -548,7 +578,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
-    launch_k(TK_ADJ, k_adj_p4, gm, blk, lcm, s, a);
+    launch_k(TK_ADJ, kp4, gm, blk, lcm, s, a);
     hipLaunchKernelGGL(k_adj_loss_part, dim3(kLossBlocks), blk, 0, s, a, nb);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(kLossBlocks), 0, s, a);
     if (grads) {

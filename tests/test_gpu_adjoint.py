@@ -47,7 +47,7 @@ def test_gradient_subset_matches_oracle():
     assert rel_l2(gp, gpo) < 1e-3
 
 
-@pytest.mark.parametrize("N,M,subpixel", [(64, 1, 1), (128, 2, 0), (256, 3, 1)])
+@pytest.mark.parametrize("N,M,subpixel", [(64, 1, 1), (128, 2, 0), (256, 3, 1), (192, 5, 1), (32, 8, 0)])
 def test_gradient_larger_probes(N, M, subpixel):
     w = wl.small_case(120 + N, 2 * N, N, M, 7, subpixel=bool(subpixel), name="g")
     O = w.O0.copy()
