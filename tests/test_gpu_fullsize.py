@@ -81,3 +81,43 @@ def test_full_size_batch_equals_single_sweeps(spiral):
         ep = rel_l2(jobs[b]["probe"].cpu().numpy(), p.cpu().numpy())
         print(f"job {b}: batch vs single rel L2 O {eo:.2e} P {ep:.2e}")
         assert eo < 1e-5 and ep < 1e-5
+
+
+@pytest.fixture(scope="module")
+def refine_w():
+    return wl.refine_case(seed=2)
+
+
+@pytest.mark.parametrize("k,refine", [(1, 0), (1599, 0), (800, 1)])
+def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine):
+    """The subpixel (four-launch) step at full size, from the GPU's own state
+    after k positions: box and probe after one more position match the
+    oracle; with refinement, the registered shift drives the same first Adam
+    step (the registration's peaks are exact)."""
+    w = refine_w
+    prm = dict(w.params, iterations=1, refine=refine, subpixel=1)
+    J1 = 1
+    ad = lambda n: np.zeros((n, 4), np.float32) if refine else None
+    st = run_gpu(_prefix(w, k), prm, adam=ad(k))
+    assert st["status"] == 0
+    step = wl.Workload(w.name, w.O_true, w.P_true, w.pos_true[k:k + J1], w.I[k:k + J1], st["O"], st["P"],
+                       w.pos0[k:k + J1], w.params)
+    g = run_gpu(step, prm, adam=ad(J1))
+    ref = oracle.rpie64(st["O"], st["P"], w.pos0[k:k + J1].astype(np.float64), w.I[k:k + J1],
+                        oracle.Params(**prm))
+    ny, nx = (int(v) for v in np.floor(w.pos0[k] + 0.5))
+    N = w.P0.shape[-1]
+    box = (slice(ny, ny + N), slice(nx, nx + N))
+    dO_g, dO_o = g["O"][box] - st["O"][box], ref["O"][box] - st["O"][box]
+    dP_g, dP_o = g["P"] - st["P"], ref["P"] - st["P"]
+    e_box, e_dO, e_dP = rel_l2(g["O"][box], ref["O"][box]), rel_l2(dO_g, dO_o), rel_l2(dP_g, dP_o)
+    print(f"k={k} refine={refine}: box {e_box:.2e} dO {e_dO:.2e} dP {e_dP:.2e}")
+    assert e_box < 1e-5 and rel_l2(g["P"], ref["P"]) < 1e-5
+    assert e_dO < 2e-5 and e_dP < 2e-5
+    outside = np.ones(g["O"].shape, bool)
+    outside[box] = False
+    assert np.array_equal(g["O"][outside], st["O"][outside])
+    if refine:
+        moved_g, moved_o = g["pos"][0] - w.pos0[k], ref["pos"][0] - w.pos0[k]
+        print(f"  Adam step gpu {moved_g} oracle {moved_o}")
+        assert np.max(np.abs(moved_g - moved_o)) < 1e-4

@@ -22,6 +22,8 @@ SP_CASES = {
     "n128m2": dict(seed=102, H=320, N=128, M=2, J=16),
     "n192m3": dict(seed=103, H=384, N=192, M=3, J=8),
     "n256m3": dict(seed=104, H=512, N=256, M=3, J=8),
+    "n32m8_rect": dict(seed=105, H=96, W=80, N=32, M=8, J=16),
+    "n64m5_rect": dict(seed=106, H=160, W=224, N=64, M=5, J=20),
 }
 
 
