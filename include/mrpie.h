@@ -18,8 +18,9 @@
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
  *    default stream) and performs no host<->device synchronisation and no
  *    device-memory allocation, so it may be recorded into a HIP graph (the
- *    refining sweep also forks work to an internal stream and joins it
- *    back, see mrpie_rpie).
+ *    refining sweep and batched calls of two or more jobs also fork work to
+ *    an internal stream and join it back before returning control of
+ *    `stream`, see mrpie_rpie and mrpie_rpie_batched).
  *  - The object O is [H][W]; probe modes P are [M][N][N]; positions are
  *    [J][2] floats (y, x): the top-left corner of the N x N box in object
  *    pixels; diffraction intensities are [J][N][N] in FFT order (zero
@@ -160,8 +161,12 @@ typedef struct {
  * of a mrpie_rpie call on that job alone to float rounding (the single-job
  * column pass keeps its first and last FFT stages in registers; jobs that
  * run the one-workgroup LDS sweep in both are bitwise equal); the error
- * curve may differ in the summation order of its partial sums.  `jobs` is a HOST array read during
- * the call. */
+ * curve may differ in the summation order of its partial sums.  With two
+ * or more jobs, every second job runs on an internal non-blocking stream
+ * (default priority) forked from `stream` and joined back into it, so two
+ * lock-step launch sequences share the GPU; while `stream` is being
+ * captured into a graph, all launches stay on `stream`.  `jobs` is a HOST
+ * array read during the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
 
 /* Launch shape of the sweep's two passes, per probe size N and call class

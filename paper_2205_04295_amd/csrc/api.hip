@@ -58,6 +58,11 @@ Side g_side[kMaxDevices];
 std::mutex g_side_mu;
 }  // namespace
 
+std::mutex& side_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
 int side_stream(hipStream_t* out, hipEvent_t** events) {
   int dev = 0;
   MRPIE_HIP(hipGetDevice(&dev));

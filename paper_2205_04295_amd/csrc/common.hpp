@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "mrpie.h"
@@ -185,9 +186,12 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 hipError_t ensure_lds(const void* kernel, size_t bytes);
 
 // The current device's side stream (non-blocking, default priority) and
-// its ring of kSideEvents events (no timing), created on first use.
+// its ring of kSideEvents events (no timing), created on first use.  A call
+// that forks work onto it holds side_mutex() while it issues that work, so
+// calls from several host threads do not interleave their event records.
 constexpr int kSideEvents = 16;
 int side_stream(hipStream_t* out, hipEvent_t** events);
+std::mutex& side_mutex();
 
 // ---------------------------------------------------------------- timing
 // Sampled per-kernel timing (diagnostic): when enabled, every `stride`-th
