@@ -919,19 +919,13 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
     MRPIE_HIP(hipEventRecord(ev[0], s));
     MRPIE_HIP(hipStreamWaitEvent(s2, ev[0], 0));
   }
-  if (!lj.empty()) {
-    rc = run_lds_sweep(c, lj.data(), (int)lj.size(), le.data(), s2 ? s2 : s);
-    if (rc) return rc;
-  }
-  if (!pj.empty()) {
-    rc = run_passes(c, pj.data(), (int)pj.size(), pe.data(), s, pj.size() >= 2 ? s2 : nullptr);
-    if (rc) return rc;
-  }
-  if (s2) {
+  if (!lj.empty()) rc = run_lds_sweep(c, lj.data(), (int)lj.size(), le.data(), s2 ? s2 : s);
+  if (!rc && !pj.empty()) rc = run_passes(c, pj.data(), (int)pj.size(), pe.data(), s, pj.size() >= 2 ? s2 : nullptr);
+  if (s2) {  // joined also after an error, so `s` never runs ahead of the side stream's work
     MRPIE_HIP(hipEventRecord(ev[1], s2));
     MRPIE_HIP(hipStreamWaitEvent(s, ev[1], 0));
   }
-  return MRPIE_OK;
+  return rc;
 }
 
 // Workspace of mrpie_rpie: the sweep layout, then (refinement only) the
@@ -990,6 +984,17 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
     hipEvent_t* ev = nullptr;
     std::unique_lock<std::mutex> lk;
     int evn = 0;
+    // `s` waits for everything issued on the side stream so far
+    auto join = [&]() -> hipError_t {
+      hipEvent_t e = ev[evn++ % kSideEvents];
+      hipError_t r = hipEventRecord(e, s2);
+      return r == hipSuccess ? hipStreamWaitEvent(s, e, 0) : r;
+    };
+    // an error after the fork returns only once the side stream is joined
+    auto fail_joined = [&](int code) {
+      (void)join();
+      return code;
+    };
     const size_t NN = (size_t)jb.N * jb.N;
     for (int it = 0; it < jb.T; ++it) {
       const int it_abs = pr->iter_offset + it;
@@ -1007,17 +1012,16 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
       for (int k = 0; k < nch; ++k) {
         const int p0 = k * kRegChunk, p1 = std::min(jb.J, p0 + kRegChunk);
         rc = run_sweep_subpixel_range(c, jb, ex, it * jb.J + p0, it * jb.J + p1, k == 0, k == nch - 1, s);
-        if (rc) return rc;
+        if (rc) return fail_joined(rc);
         hipEvent_t e = ev[evn++ % kSideEvents];
-        MRPIE_HIP(hipEventRecord(e, s));
-        MRPIE_HIP(hipStreamWaitEvent(s2, e, 0));
+        hipError_t he = hipEventRecord(e, s);
+        if (he == hipSuccess) he = hipStreamWaitEvent(s2, e, 0);
+        if (he != hipSuccess) return fail_joined(hip_fail(he, "side-stream fork"));
         rc = run_register(jb.N, p1 - p0, ex.reg_ref + p0 * NN, ex.reg_mov + p0 * NN, pr->upsample, pr->xcorr_norm,
                           shift + 2 * (size_t)p0, peak + 4 * (size_t)p0, jb.ws + R.reg, reg_bytes, s2);
-        if (rc) return rc;
+        if (rc) return fail_joined(rc);
       }
-      hipEvent_t e = ev[evn++ % kSideEvents];
-      MRPIE_HIP(hipEventRecord(e, s2));
-      MRPIE_HIP(hipStreamWaitEvent(s, e, 0));
+      MRPIE_HIP(join());
       rc = launch_adam(jb.J, (float*)jb.pos, adam, shift, it_abs - pr->refine_start + 1, pr, jb.H - jb.N,
                        jb.W - jb.N, s);
       if (rc) return rc;
