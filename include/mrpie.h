@@ -162,9 +162,10 @@ typedef struct {
  * column pass keeps its first and last FFT stages in registers; jobs that
  * run the one-workgroup LDS sweep in both are bitwise equal); the error
  * curve may differ in the summation order of its partial sums.  With two
- * or more jobs, every second job runs on an internal non-blocking stream
- * (default priority) forked from `stream` and joined back into it, so two
- * lock-step launch sequences share the GPU; while `stream` is being
+ * or more jobs, every second job runs on the internal non-blocking stream
+ * described at mrpie_rpie, forked from `stream` and joined back into it
+ * before the call returns, so two lock-step launch sequences share the GPU
+ * (jobs whose modes fit the LDS run their one-workgroup sweep there too); while `stream` is being
  * captured into a graph, all launches stay on `stream`.  `jobs` is a HOST
  * array read during the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
