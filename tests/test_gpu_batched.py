@@ -84,3 +84,42 @@ def test_batched_many_jobs_in_place_passes():
     o = run_oracle(ws[4], prm)
     assert rel_l2(jobs[4]["obj"].cpu().numpy(), o["O"]) < 1e-4
     assert rel_l2(jobs[4]["probe"].cpu().numpy(), o["P"]) < 1e-4
+
+
+def test_batched_calls_from_two_host_threads():
+    """Two host threads issue batched calls on two streams at once (both fork
+    the library's side stream): every job ends bitwise equal to the same call
+    made alone."""
+    import threading
+    from paper_2205_04295_amd import api
+    specs = [dict(seed=91, H=256, N=128, M=2, J=6), dict(seed=92, H=192, N=64, M=3, J=8),
+             dict(seed=93, H=320, N=128, M=1, J=5)]
+    ws = [wl.small_case(name=f"t{i}", **s) for i, s in enumerate(specs)]
+    prm = dict(ws[0].params, iterations=2)
+
+    def jobs():
+        return [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"]) for d in map(to_dev, ws)]
+    ref = jobs()
+    api.rpie_batched(ref, **prm)
+    torch.cuda.synchronize()
+    runs = [jobs(), jobs()]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()  # inputs uploaded on the default stream
+    errors = []
+
+    def work(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                api.rpie_batched(runs[k], stream=streams[k], **prm)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors
+    for run in runs:
+        for a, b in zip(run, ref):
+            assert torch.equal(a["obj"], b["obj"]) and torch.equal(a["probe"], b["probe"])
