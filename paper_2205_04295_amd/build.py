@@ -28,6 +28,7 @@ FLAGS = [
 # kernel-argument fetch at the start of every launch.
 FILE_FLAGS = {
     "sweep.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=16"],
+    "sweep_sp.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=16"],
 }
 
 

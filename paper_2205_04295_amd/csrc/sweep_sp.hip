@@ -412,6 +412,20 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
 }
 
 // ---------------------------------------------------------------- kernels
+// The job comes as leading scalar arguments (positions, workspace, object,
+// probe, tick, mode, shape), which gfx950 preloads into SGPRs, so a launch's
+// first loads do not wait for a kernel-argument fetch; the rest follows.
+#define MRPIE_SP_PARAMS                                                                                        \
+  const float *pos, char *ws, float2 *obj, float2 *probe, int t, int mode, int J, int T, int NM, int H, int W, \
+      const float *I, int *status, float2 *reg_ref, float2 *reg_mov, int subpixel, int record_start, const Common c
+#define MRPIE_SP_ARGS                                                                                  \
+  SpArgs a;                                                                                            \
+  a.c = c;                                                                                             \
+  a.jb = JobRec{obj, probe, pos, I, ws, status, H, W, NM & 0xffff, NM >> 16, J, T};                    \
+  a.subpixel = subpixel;                                                                               \
+  a.reg_ref = reg_ref;                                                                                 \
+  a.reg_mov = reg_mov;                                                                                 \
+  a.record_start = record_start;
 #define MRPIE_DISPATCH(FN, ...)              \
   switch (a.jb.N) {                          \
     case 32: FN<32>(__VA_ARGS__); break;     \
@@ -421,20 +435,24 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
     default: FN<256>(__VA_ARGS__); break;    \
   }
 
-__global__ __launch_bounds__(256) void k_sp_rows_gather(const SpArgs a, int t, int mode) {
+__global__ __launch_bounds__(256) void k_sp_rows_gather(MRPIE_SP_PARAMS) {
   extern __shared__ float2 smem[];
+  MRPIE_SP_ARGS
   MRPIE_DISPATCH(sp_rows_gather, a, t, mode, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_cols_exit(const SpArgs a, int t) {
+__global__ __launch_bounds__(256) void k_sp_cols_exit(MRPIE_SP_PARAMS) {
   extern __shared__ float2 smem[];
+  MRPIE_SP_ARGS
   MRPIE_DISPATCH(sp_cols_exit, a, t, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_rows_mod(const SpArgs a, int t) {
+__global__ __launch_bounds__(256) void k_sp_rows_mod(MRPIE_SP_PARAMS) {
   extern __shared__ float2 smem[];
+  MRPIE_SP_ARGS
   MRPIE_DISPATCH(sp_rows_mod, a, t, smem)
 }
-__global__ __launch_bounds__(256) void k_sp_cols_update(const SpArgs a, int t) {
+__global__ __launch_bounds__(256) void k_sp_cols_update(MRPIE_SP_PARAMS) {
   extern __shared__ float2 smem[];
+  MRPIE_SP_ARGS
   MRPIE_DISPATCH(sp_cols_update, a, t, smem)
 }
 
@@ -447,27 +465,25 @@ int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelEx
                              bool tail, hipStream_t s) {
   int rc = launch_init_twiddles(s);
   if (rc) return rc;
-  SpArgs a{};
-  a.c = c;
-  a.jb = jb;
-  a.subpixel = ex.subpixel;
-  a.reg_ref = ex.reg_ref;
-  a.reg_mov = ex.reg_mov;
-  a.record_start = ex.record_start;
   const int N = jb.N, M = jb.M;
+  const int NM = N | (M << 16);
   const size_t lg = (size_t)(N + N + 4 * N) * 8;
   const size_t lm = (size_t)(N + 2 * M * N) * 8;
   MRPIE_HIP(ensure_lds((const void*)k_sp_cols_exit, lm));
   MRPIE_HIP(ensure_lds((const void*)k_sp_rows_mod, lm));
   MRPIE_HIP(ensure_lds((const void*)k_sp_cols_update, lm));
   const dim3 g(N), blk(256);
+#define MRPIE_SP_LAUNCH(K, L, T_, MODE)                                                                        \
+  hipLaunchKernelGGL(K, g, blk, L, s, jb.pos, jb.ws, jb.obj, jb.probe, T_, MODE, jb.J, jb.T, NM, jb.H, jb.W, jb.I, \
+                     jb.status, ex.reg_ref, ex.reg_mov, ex.subpixel, ex.record_start, c)
   for (int t = t0; t < t1; ++t) {
-    hipLaunchKernelGGL(k_sp_rows_gather, g, blk, lg, s, a, t, (t == t0 && head) ? 0 : 1);
-    hipLaunchKernelGGL(k_sp_cols_exit, g, blk, lm, s, a, t);
-    hipLaunchKernelGGL(k_sp_rows_mod, g, blk, lm, s, a, t);
-    hipLaunchKernelGGL(k_sp_cols_update, g, blk, lm, s, a, t);
+    MRPIE_SP_LAUNCH(k_sp_rows_gather, lg, t, (t == t0 && head) ? 0 : 1);
+    MRPIE_SP_LAUNCH(k_sp_cols_exit, lm, t, 0);
+    MRPIE_SP_LAUNCH(k_sp_rows_mod, lm, t, 0);
+    MRPIE_SP_LAUNCH(k_sp_cols_update, lm, t, 0);
   }
-  if (tail) hipLaunchKernelGGL(k_sp_rows_gather, g, blk, lg, s, a, t1, 2);
+  if (tail) MRPIE_SP_LAUNCH(k_sp_rows_gather, lg, t1, 2);
+#undef MRPIE_SP_LAUNCH
   MRPIE_HIP(hipGetLastError());
   return MRPIE_OK;
 }
