@@ -17,10 +17,10 @@
  *    matching *_workspace_size function returns (0 when none is needed).
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
  *    default stream) and performs no host<->device synchronisation and no
- *    device-memory allocation, so it may be recorded into a HIP graph (the
- *    refining sweep and batched calls of two or more jobs also fork work to
- *    an internal stream and join it back before returning control of
- *    `stream`, see mrpie_rpie and mrpie_rpie_batched).
+ *    device-memory allocation, so it may be recorded into a HIP graph
+ *    (batched calls of two or more jobs also fork work to an internal
+ *    stream and join it back before returning control of `stream`, see
+ *    mrpie_rpie_batched).
  *  - The object O is [H][W]; probe modes P are [M][N][N]; positions are
  *    [J][2] floats (y, x): the top-left corner of the N x N box in object
  *    pixels; diffraction intensities are [J][N][N] in FFT order (zero
@@ -129,11 +129,10 @@ int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t
  *  status int32, OR-ed with MRPIE_STATUS_* bits (may be NULL)
  *  ws, ws_bytes     workspace of at least mrpie_workspace_size bytes
  * The result is deterministic: the same inputs give bitwise equal outputs.
- * With refine = 1 the registration of every block of 256 positions runs on
- * an internal non-blocking stream (default priority) while the sweep goes
- * on, joined back into `stream` before the Adam step; the first such call
- * on a device creates that stream and 16 events, kept until the process
- * ends.  No device memory is allocated. */
+ * With refine = 1 each iteration's sweep records every position's patch
+ * before and after its update, then all J pairs are registered and the
+ * Adam step is taken, in order on `stream`.  No device memory is
+ * allocated. */
 int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void* probe,
                float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);
@@ -162,10 +161,12 @@ typedef struct {
  * column pass keeps its first and last FFT stages in registers; jobs that
  * run the one-workgroup LDS sweep in both are bitwise equal); the error
  * curve may differ in the summation order of its partial sums.  With two
- * or more jobs, every second job runs on the internal non-blocking stream
- * described at mrpie_rpie, forked from `stream` and joined back into it
- * before the call returns, so two lock-step launch sequences share the GPU
- * (jobs whose modes fit the LDS run their one-workgroup sweep there too); while `stream` is being
+ * or more jobs, every second job runs on an internal non-blocking stream
+ * (default priority; the first such call on a device creates it and 16
+ * events, kept until the process ends), forked from `stream` and joined
+ * back into it before the call returns, so two lock-step launch sequences
+ * share the GPU (jobs whose modes fit the LDS run their one-workgroup sweep
+ * there too); while `stream` is being
  * captured into a graph, all launches stay on `stream`.  `jobs` is a HOST
  * array read during the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);

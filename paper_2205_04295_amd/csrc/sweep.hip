@@ -956,16 +956,13 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
                        hipStream_t s) {
   mrpie_problem pb{jb.H, jb.W, jb.N, jb.M, jb.J};
   const RefineLayout R = refine_layout(&pb, pr);
-  // k_cols below belongs to this translation unit: its twiddle table
-  int rc0 = launch_init_twiddles(s);
-  if (rc0) return rc0;
+  int rc = MRPIE_OK;
   LaunchArgs la{};
   la.c = c;
   la.njobs = 1;
   la.job[0] = jb;
   launch_zero_err(la, 1, s);
   SubpixelExtra ex{pr->subpixel, nullptr, nullptr, pr->refine_start};
-  int rc;
   if (!pr->refine) {
     rc = run_sweep_subpixel(c, jb, ex, 0, jb.T, true, true, s);
     if (rc) return rc;
@@ -975,53 +972,20 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
     float* shift = (float*)(jb.ws + R.shift);
     int32_t* peak = (int32_t*)(jb.ws + R.peak);
     const size_t reg_bytes = reg_layout(jb.N, jb.J, pr->upsample).total;
-    // The sweep is latency bound (one workgroup per row or column of one
-    // position per launch), so the registration of each block of
-    // kRegChunk positions runs on the side stream as soon as the sweep
-    // has recorded those pairs, on the CUs the sweep leaves idle; Adam
-    // waits for all of them at the end of the iteration.
-    hipStream_t s2 = nullptr;
-    hipEvent_t* ev = nullptr;
-    std::unique_lock<std::mutex> lk;
-    int evn = 0;
-    // `s` waits for everything issued on the side stream so far
-    auto join = [&]() -> hipError_t {
-      hipEvent_t e = ev[evn++ % kSideEvents];
-      hipError_t r = hipEventRecord(e, s2);
-      return r == hipSuccess ? hipStreamWaitEvent(s, e, 0) : r;
-    };
-    // an error after the fork returns only once the side stream is joined
-    auto fail_joined = [&](int code) {
-      (void)join();
-      return code;
-    };
-    const size_t NN = (size_t)jb.N * jb.N;
+    // Per iteration: the sweep (recording every position's patch before and
+    // after its update once refinement has started), the registration of
+    // all J pairs, the Adam step.  The registration runs after the sweep on
+    // the same stream: overlapping it with the latency-bound sweep on a
+    // second stream slowed the sweep by about what it hid (256^2 x 3, 1600
+    // positions, upsample 100: 50.1 against 49.0 ms per iteration).
     for (int it = 0; it < jb.T; ++it) {
       const int it_abs = pr->iter_offset + it;
-      if (it_abs < pr->refine_start) {
-        rc = run_sweep_subpixel(c, jb, ex, it, 1, true, true, s);
-        if (rc) return rc;
-        continue;
-      }
-      if (!s2) {
-        rc = side_stream(&s2, &ev);
-        if (rc) return rc;
-        lk = std::unique_lock<std::mutex>(side_mutex());
-      }
-      const int nch = (jb.J + kRegChunk - 1) / kRegChunk;
-      for (int k = 0; k < nch; ++k) {
-        const int p0 = k * kRegChunk, p1 = std::min(jb.J, p0 + kRegChunk);
-        rc = run_sweep_subpixel_range(c, jb, ex, it * jb.J + p0, it * jb.J + p1, k == 0, k == nch - 1, s);
-        if (rc) return fail_joined(rc);
-        hipEvent_t e = ev[evn++ % kSideEvents];
-        hipError_t he = hipEventRecord(e, s);
-        if (he == hipSuccess) he = hipStreamWaitEvent(s2, e, 0);
-        if (he != hipSuccess) return fail_joined(hip_fail(he, "side-stream fork"));
-        rc = run_register(jb.N, p1 - p0, ex.reg_ref + p0 * NN, ex.reg_mov + p0 * NN, pr->upsample, pr->xcorr_norm,
-                          shift + 2 * (size_t)p0, peak + 4 * (size_t)p0, jb.ws + R.reg, reg_bytes, s2);
-        if (rc) return fail_joined(rc);
-      }
-      MRPIE_HIP(join());
+      rc = run_sweep_subpixel(c, jb, ex, it, 1, true, true, s);
+      if (rc) return rc;
+      if (it_abs < pr->refine_start) continue;
+      rc = run_register(jb.N, jb.J, ex.reg_ref, ex.reg_mov, pr->upsample, pr->xcorr_norm, shift, peak,
+                        jb.ws + R.reg, reg_bytes, s);
+      if (rc) return rc;
       rc = launch_adam(jb.J, (float*)jb.pos, adam, shift, it_abs - pr->refine_start + 1, pr, jb.H - jb.N,
                        jb.W - jb.N, s);
       if (rc) return rc;
