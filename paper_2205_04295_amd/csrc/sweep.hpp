@@ -76,9 +76,11 @@ struct Tuning {
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int nb, const Tuning& t);
 
-// Subpixel / refining sweep (four launches per position).  `reg_ref`,
+// Subpixel / refining sweep (four launches per position): iterations
+// [it0, it0 + iters) of job `jb`; head: the first step has no previous one,
+// tail: the last step's update is applied before returning.  `reg_ref`,
 // `reg_mov` ([J][N][N] each) receive the patch before and after its update
-// when `record` is set.
+// from iteration record_start on, when set.
 struct SubpixelExtra {
   int subpixel;      // 0: fractions forced to 0 (refinement on integer crops)
   float2* reg_ref;
@@ -87,10 +89,6 @@ struct SubpixelExtra {
 };
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s);
-// The same for position ticks [t0, t1) (t = iteration * J + position); head:
-// t0 starts a call (no previous step), tail: t1 ends it.
-int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int t0, int t1, bool head,
-                             bool tail, hipStream_t s);
 size_t rpie_ws_total(const mrpie_problem* pb, const mrpie_params* pr);
 int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr, float* adam, float* err_out,
                        hipStream_t s);

@@ -458,11 +458,7 @@ __global__ __launch_bounds__(256) void k_sp_cols_update(MRPIE_SP_PARAMS) {
 
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s) {
-  return run_sweep_subpixel_range(c, jb, ex, it0 * jb.J, (it0 + iters) * jb.J, head, tail, s);
-}
-
-int run_sweep_subpixel_range(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int t0, int t1, bool head,
-                             bool tail, hipStream_t s) {
+  const int t0 = it0 * jb.J, t1 = (it0 + iters) * jb.J;
   int rc = launch_init_twiddles(s);
   if (rc) return rc;
   const int N = jb.N, M = jb.M;
