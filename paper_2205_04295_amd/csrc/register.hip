@@ -196,12 +196,20 @@ __global__ void k_reg_kmat(const RegArgs a, int N) {
   }
 }
 
+// Register blocks of the two GEMMs: RB = 4 (64 x 64 output tiles, 16
+// complex FMAs per 8 LDS reads) for large windows, RB = 2 (32-row tiles)
+// for small ones, whose last 64-row tile would be mostly empty (upsample
+// 1000, 256 pairs: 28.6 against 35.0 ms; upsample 100: 1.77 against 1.82
+// ms with RB = 2).  Every output sums its terms in k order whatever RB is.
+inline int gemm_rb(int U) { return U > 320 ? 4 : 2; }
+
 // T[b][u][kx] = sum_ky K[u][ky] X[b][ky][kx] e^{2 pi i (ky s0y + kx s0x)/N}
-// Tile: 32 u x 64 kx per workgroup, ky in chunks of 16 staged in LDS; each
-// thread accumulates a 2 x 4 block.
-constexpr int G1_TU = 32, G1_TX = 64, G1_KC = 16;
-template <int N>
+// Tile: 16 RB u x 64 kx per workgroup, ky in chunks of 16 staged in LDS;
+// each of the 16 x 16 threads accumulates an RB x 4 block.
+constexpr int G1_RJ = 4, G1_TX = 16 * G1_RJ, G1_KC = 16;
+template <int N, int G1_RI>
 __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
+  constexpr int G1_TU = 16 * G1_RI;
   __shared__ double2 Ks[G1_TU][G1_KC + 1];
   __shared__ double2 Xs[G1_KC][G1_TX + 1];
   __shared__ double2 tw[N];  // exp(-2 pi i e / N): the lag phase is an N-th root of unity
@@ -211,11 +219,11 @@ __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
   const double2* X = a.work + ((size_t)b * 2 + 1) * N * N;
   const int s0y = a.s0[2 * b], s0x = a.s0[2 * b + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // 16 x 16 threads
-  double2 acc[2][4];
+  double2 acc[G1_RI][G1_RJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < G1_RI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int j = 0; j < G1_RJ; ++j) acc[i][j] = make_double2(0.0, 0.0);
   load_twiddles<N>(tw);
   __syncthreads();
   for (int k0 = 0; k0 < N; k0 += G1_KC) {
@@ -237,15 +245,15 @@ __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < G1_KC; ++kk) {
-      double2 kv[2], xv[4];
+      double2 kv[G1_RI], xv[G1_RJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) kv[i] = Ks[ty + 16 * i][kk];
+      for (int i = 0; i < G1_RI; ++i) kv[i] = Ks[ty + 16 * i][kk];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xv[j] = Xs[kk][tx + 16 * j];
+      for (int j = 0; j < G1_RJ; ++j) xv[j] = Xs[kk][tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < G1_RI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < G1_RJ; ++j) {
           acc[i][j].x = fma(kv[i].x, xv[j].x, fma(-kv[i].y, xv[j].y, acc[i][j].x));
           acc[i][j].y = fma(kv[i].x, xv[j].y, fma(kv[i].y, xv[j].x, acc[i][j].y));
         }
@@ -254,20 +262,21 @@ __global__ __launch_bounds__(256) void k_reg_gemm1(const RegArgs a) {
   }
   double2* T = a.T + (size_t)b * U * N;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < G1_RI; ++i) {
     const int u = u0 + ty + 16 * i;
     if (u >= U) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < G1_RJ; ++j)
       if (x0 + tx + 16 * j < N) T[(size_t)u * N + x0 + tx + 16 * j] = acc[i][j];
   }
 }
 
 // C[b][u][v] = sum_kx T[b][u][kx] K[v][kx]; per-tile first maximum of |C|^2.
-// Tile 32 u x 32 v, kx in chunks of 16; each thread a 2 x 2 block.
-constexpr int G2_T = 32, G2_KC = 16;
-template <int N>
+// Tile 16 RB u x 16 RB v, kx in chunks of 16; each thread an RB x RB block.
+constexpr int G2_KC = 16;
+template <int N, int G2_R>
 __global__ __launch_bounds__(256) void k_reg_gemm2(const RegArgs a) {
+  constexpr int G2_T = 16 * G2_R;
   __shared__ double2 Ts[G2_T][G2_KC + 1];
   __shared__ double2 Ks[G2_T][G2_KC + 1];
   __shared__ double rv[16];
@@ -277,11 +286,11 @@ __global__ __launch_bounds__(256) void k_reg_gemm2(const RegArgs a) {
   const int U = a.U;
   const double2* T = a.T + (size_t)b * U * N;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double2 acc[2][2];
+  double2 acc[G2_R][G2_R];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < G2_R; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int j = 0; j < G2_R; ++j) acc[i][j] = make_double2(0.0, 0.0);
   for (int k0 = 0; k0 < N; k0 += G2_KC) {
     for (int i = threadIdx.x; i < G2_T * G2_KC; i += blockDim.x) {
       const int rr = i / G2_KC, kk = i - rr * G2_KC;
@@ -292,15 +301,15 @@ __global__ __launch_bounds__(256) void k_reg_gemm2(const RegArgs a) {
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < G2_KC; ++kk) {
-      double2 tv[2], kv[2];
+      double2 tv[G2_R], kv[G2_R];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) tv[i] = Ts[ty + 16 * i][kk];
+      for (int i = 0; i < G2_R; ++i) tv[i] = Ts[ty + 16 * i][kk];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) kv[j] = Ks[tx + 16 * j][kk];
+      for (int j = 0; j < G2_R; ++j) kv[j] = Ks[tx + 16 * j][kk];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < G2_R; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < G2_R; ++j) {
           acc[i][j].x = fma(tv[i].x, kv[j].x, fma(-tv[i].y, kv[j].y, acc[i][j].x));
           acc[i][j].y = fma(tv[i].x, kv[j].y, fma(tv[i].y, kv[j].x, acc[i][j].y));
         }
@@ -310,9 +319,9 @@ __global__ __launch_bounds__(256) void k_reg_gemm2(const RegArgs a) {
   double best = -1.0;
   long long bi = (long long)U * U;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < G2_R; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < G2_R; ++j) {
       const int u = u0 + ty + 16 * i, v = v0 + tx + 16 * j;
       if (u < U && v < U) {
         const double m = cabs2(acc[i][j]);
@@ -382,7 +391,8 @@ RegLayout reg_layout(int N, int B, int up) {
   int U, c;
   reg_window(up, &U, &c);
   const int chunk = std::max(1, std::min(B, kRegChunk));
-  const int tiles = ((U + G2_T - 1) / G2_T) * ((U + G2_T - 1) / G2_T);
+  const int t2 = 16 * gemm_rb(U);
+  const int tiles = ((U + t2 - 1) / t2) * ((U + t2 - 1) / t2);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = ws_align(off + bytes); return o; };
   L.chunk = chunk;
@@ -418,7 +428,9 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
   a.tile_i = (long long*)(ws + L.tile_i);
   MRPIE_HIP(ensure_lds((const void*)k_reg_cols<N>, reg_cols_lds(N)));
   hipLaunchKernelGGL(k_reg_kmat, dim3(64), dim3(256), 0, s, a, N);
-  const int gt = (U + G2_T - 1) / G2_T;
+  const int rb = gemm_rb(U), gt = (U + 16 * rb - 1) / (16 * rb);
+  const auto kg1 = rb == 4 ? k_reg_gemm1<N, 4> : k_reg_gemm1<N, 2>;
+  const auto kg2 = rb == 4 ? k_reg_gemm2<N, 4> : k_reg_gemm2<N, 2>;
   for (int b0 = 0; b0 < B; b0 += L.chunk) {
     const int nb = std::min(L.chunk, B - b0);
     a.B = nb;
@@ -430,8 +442,8 @@ static int register_impl(int B, const float2* ref, const float2* mov, int up, in
     launch_k(TK_REG, k_reg_cols<N>, dim3(N / kRegCW, nb), dim3(256), reg_cols_lds(N), s, a);
     hipLaunchKernelGGL(k_reg_coarse<N>, dim3(N / kRegRW, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_s0, dim3(nb), dim3(256), 0, s, a, N);
-    launch_k(TK_GEMM, k_reg_gemm1<N>, dim3((N + G1_TX - 1) / G1_TX, (U + G1_TU - 1) / G1_TU, nb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_reg_gemm2<N>, dim3(gt, gt, nb), dim3(256), 0, s, a);
+    launch_k(TK_GEMM, kg1, dim3((N + G1_TX - 1) / G1_TX, (U + 16 * rb - 1) / (16 * rb), nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kg2, dim3(gt, gt, nb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reg_final, dim3((nb + 63) / 64), dim3(64), 0, s, a, gt * gt);
   }
   MRPIE_HIP(hipGetLastError());

@@ -122,3 +122,17 @@ def test_adam_matches_oracle():
         torch.cuda.synchronize()
         assert np.allclose(tp.cpu().numpy(), po, atol=1e-4)
         assert np.allclose(ts.cpu().numpy(), so, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("N,up", [(256, 1000), (128, 500)])
+def test_register_peaks_exact_large_windows(N, up):
+    """Upsampling factors whose window (U = ceil(1.5 up) > 320 lags) takes
+    the GEMMs' 64 x 64 output tiles: peaks equal the oracle's."""
+    rng = np.random.default_rng(N + up)
+    B = 3
+    ref, mov, s = pairs_shifted(rng, B, N, noise=0.1)
+    sh, pk = gpu_register(ref, mov, up, 0)
+    for b in range(B):
+        so, po = oracle.register64(ref[b].astype(np.complex128), mov[b].astype(np.complex128), up, 0)
+        assert list(pk[b]) == list(po), (b, pk[b], po)
+        assert np.allclose(sh[b], so, atol=1e-6)
