@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "319d97f3e8e58874007409172fda8e90251d0e86717d1973ea96b98ec2f2f53e",
+    "sha256": "4e33f0577b59afb1b2872dc10754bb836a4f6d2855c92e13680888ade2ee29f1",
     "fetch_factor": 2.000, "write_factor": 1.000,
     "k_rows": {"fetch_kib": 3455.5, "write_kib": 4097.6},
     "k_cols": {"fetch_kib": 1005.5, "write_kib": 1552.0},
