@@ -88,10 +88,11 @@ __global__ __launch_bounds__(256) void k_reg_rows(const RegArgs a) {
 
 // CW adjacent columns per workgroup, so every access moves CW * 16
 // contiguous bytes of a row; pixel q of the group is row k = q / CW, column
-// c = q % CW.  LDS (dynamic): twiddles, then two ping-pong buffers of 2 CW
-// transforms (ref and mov of each column).
+// c = q % CW.  LDS (dynamic): twiddles, then one buffer of 2 CW transforms
+// (ref and mov of each column) transformed in place (the same butterflies
+// as the ping-pong plan, half the LDS: twice the workgroups per CU).
 constexpr int kRegCW = 4;
-constexpr size_t reg_cols_lds(int N) { return (size_t)(N + 2 * 2 * kRegCW * N) * 16; }
+constexpr size_t reg_cols_lds(int N) { return (size_t)(N + 2 * kRegCW * N) * 16; }
 
 template <int N>
 __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
@@ -99,7 +100,6 @@ __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
   extern __shared__ double2 dsm[];
   double2* tw = dsm;
   double2* A = tw + N;           // ref column c at c * N, mov at (CW + c) * N
-  double2* B = A + 2 * CW * N;
   const int u0 = blockIdx.x * CW, b = blockIdx.y, tid = threadIdx.x;
   double2* w0 = a.work + (size_t)b * 2 * N * N;  // ref spectra -> later F^-1 over columns of X
   double2* w1 = w0 + (size_t)N * N;              // mov spectra -> later X
@@ -112,8 +112,9 @@ __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
     A[(CW + c) * N + k] = w1[(size_t)k * N + u0 + c];
   }
   __syncthreads();
-  double2* F = fft_lds<N, false>(A, B, 2 * CW, tw);
-  double2* G = (F == A) ? B : A;
+  fft_lds_inplace<N, false, true, 2 * CW, 256>(A, 2 * CW, tw);
+  const double2* F = A;
+  double2* G = A;  // X over the ref transforms: each thread rewrites only the pixels it reads
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -127,7 +128,8 @@ __global__ __launch_bounds__(256) void k_reg_cols(const RegArgs a) {
     G[c * N + k] = x;
   }
   __syncthreads();
-  double2* H = fft_lds<N, true>(G, F, CW, tw);
+  fft_lds_inplace<N, true, true, CW, 256>(G, CW, tw);
+  const double2* H = G;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
