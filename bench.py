@@ -8,8 +8,8 @@ waves, forward FFT, modulus replacement, inverse FFT, probe and object
 updates) with every input resident in HBM.  The metric is positions x
 iterations per second.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on
-one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the library runs
+on one GPU.
 """
 from __future__ import annotations
 
@@ -328,7 +328,7 @@ def measure_uneven(api, torch, dev, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch

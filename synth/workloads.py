@@ -8,8 +8,8 @@ with random jitter, object and probe assembled from magnitude and phase).
 The data simulation uses ``scipy.fft``; neither the oracle nor the GPU path
 imports anything from here except the finished arrays.
 
-Shapes follow the workloads of the paper's soft-X-ray scans as restated for
-this build (a small raster case, a 1024^2 / 256^2 / 3-mode / 1600-point
+Shapes follow the workloads of the paper's soft-X-ray scans (a small raster
+case, a 1024^2 / 256^2 / 3-mode / 1600-point
 Fermat-spiral case, its position-error variant, a gradient-check subset and a
 64-job uneven batch).  All arrays handed out are complex64 / float32, the
 precision the GPU path works in; the oracle upcasts them.
