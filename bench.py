@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "4e33f0577b59afb1b2872dc10754bb836a4f6d2855c92e13680888ade2ee29f1",
+    "sha256": "8cc7357cb9fd229ce1986a8f73a3f5d117c3fb565ba5382161aea51213a3ba00",
     "fetch_factor": 2.000, "write_factor": 1.000,
     "k_rows": {"fetch_kib": 3455.5, "write_kib": 4097.6},
     "k_cols": {"fetch_kib": 1005.5, "write_kib": 1552.0},

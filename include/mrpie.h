@@ -166,9 +166,8 @@ typedef struct {
  * events, kept until the process ends), forked from `stream` and joined
  * back into it before the call returns, so two lock-step launch sequences
  * share the GPU (jobs whose modes fit the LDS run their one-workgroup sweep
- * there too); while `stream` is being
- * captured into a graph, all launches stay on `stream`.  `jobs` is a HOST
- * array read during the call. */
+ * there too); while `stream` is being captured into a graph, all launches
+ * stay on `stream`.  `jobs` is a HOST array read during the call. */
 int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
 
 /* Launch shape of the sweep's two passes, per probe size N and call class
@@ -186,7 +185,7 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * for a single sweep; 4: coalesced 32-byte row segments, for batches);
  * rows_inplace: 1 runs the inverse row FFTs of multi-job launches in place
  * (half the row pass's LDS: more workgroups per CU, one more barrier per
- * FFT stage), and the column FFTs too from 16 jobs per launch on (with
+ * FFT stage), and the column FFTs too in calls of 16 or more jobs (with
  * cols_width 4); 0 ping-pongs two buffers.  The
  * setting is process-wide host state; results do not depend on it beyond
  * float rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the

@@ -758,11 +758,11 @@ void set_tuning(int N, int nb, const Tuning& t) {
 static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 2 : 4) * M * N) * 8; }
 static size_t cols_lds(int N, int M, int cw, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * cw * M * N) * 8; }
 
-// The column pass runs in place with the row pass only from this many jobs
-// per launch on: it doubles the workgroups per CU but adds a barrier per
-// stage, which pays once the launch is throughput bound (measured at 256^2 x
-// 3: 32 jobs 122 against 134 us per lock-step position, 8 jobs 41.9 against
-// 41.1 us).
+// The column pass runs in place with the row pass only in calls of this many
+// jobs or more: it doubles the workgroups per CU but adds a barrier per
+// stage, which pays once the launches are throughput bound (measured at
+// 256^2 x 3 with one launch chain per call: 32 jobs 122 against 134 us per
+// lock-step position, 8 jobs 41.9 against 41.1 us).
 constexpr int kColsInplaceJobs = 16;
 
 void launch_zero_err(const LaunchArgs& a, int nb, hipStream_t s) {
