@@ -28,24 +28,30 @@ namespace mrpie {
 
 __device__ __forceinline__ size_t chunk_off(int b, int N) { return (size_t)b * N * N; }
 
-// P1 (rows): gather crop row r of position j0 + b, row FFT -> Cp
+// Single-field row passes take kAdjRows rows per workgroup, so that every
+// thread has a butterfly in most FFT stages (one 256-point row alone keeps
+// 32 of 256 threads busy in a radix-8 stage).
+constexpr int kAdjRows = 4;
+
+// P1 (rows): gather crop rows r0.. of position j0 + b, row FFTs -> Cp
 template <int N>
 __device__ void adj_p1(const AdjArgs& a, float2* smem) {
-  const int r = blockIdx.x, b = blockIdx.y;
+  const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
   const int j = a.j0 + b;
   float2* tw = smem;
-  float2* A = tw + N;
-  float2* B = A + N;
+  float2* A = tw + N;                // kAdjRows N
+  float2* B = A + kAdjRows * N;      // kAdjRows N
   const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
   const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
-  const int c = threadIdx.x;
-  float2 v = make_float2(0.f, 0.f);
-  if (c < N) v = a.obj[(size_t)(ny + r) * a.W + nx + c];
+  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) {
+    const int rr = i / N, c = i - rr * N;
+    A[i] = a.obj[(size_t)(ny + r0 + rr) * a.W + nx + c];
+  }
   load_twiddles<N>(tw);
-  if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, false, false>(A, B, 1, tw);
-  if (c < N) a.Cp[chunk_off(b, N) + (size_t)r * N + c] = R[c];
+  float2* R = fft_lds<N, false, false>(A, B, kAdjRows, tw);
+  float2* cp = a.Cp + chunk_off(b, N) + (size_t)r0 * N;
+  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) cp[i] = R[i];
 }
 
 __device__ __forceinline__ void frac_of(const AdjArgs& a, int j, int N, float* fy, float* fx) {
@@ -368,22 +374,19 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
   }
 }
 
-// P7 (rows): inverse row FFT -> S_{-f}(g) row r (object-gradient term)
+// P7 (rows): inverse row FFTs -> S_{-f}(g) rows r0.. (object-gradient term)
 template <int N>
 __device__ void adj_p7(const AdjArgs& a, float2* smem) {
-  const int r = blockIdx.x, b = blockIdx.y;
+  const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
   float2* tw = smem;
-  float2* A = tw + N;
-  float2* B = A + N;
-  const int c = threadIdx.x;
-  float2* g = a.G + chunk_off(b, N);
-  float2 v = make_float2(0.f, 0.f);
-  if (c < N) v = g[(size_t)r * N + c];
+  float2* A = tw + N;                // kAdjRows N
+  float2* B = A + kAdjRows * N;      // kAdjRows N
+  float2* g = a.G + chunk_off(b, N) + (size_t)r0 * N;
+  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) A[i] = g[i];
   load_twiddles<N>(tw);
-  if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, true, false>(A, B, 1, tw);
-  if (c < N) g[(size_t)r * N + c] = R[c];
+  float2* R = fft_lds<N, true, false>(A, B, kAdjRows, tw);
+  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) g[i] = R[i];
 }
 
 #define MRPIE_ADJ_KERNEL(NAME, FN)                       \
@@ -562,7 +565,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   }
   // LDS of the row passes (one / M+1 / M transforms), of the single-field
   // column passes (kAdjCW1 transforms) and of the mode column pass
-  const size_t l1 = (size_t)3 * N * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
+  const size_t l1 = (size_t)(N + 2 * kAdjRows * N) * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
   const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * N) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * N) * 8;
   MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm));
@@ -574,8 +577,8 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     a.nb = nb;
-    const dim3 g(N, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(256);
-    hipLaunchKernelGGL(k_adj_p1, g, blk, l1, s, a);
+    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(256);
+    hipLaunchKernelGGL(k_adj_p1, gr, blk, l1, s, a);
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
     launch_k(TK_ADJ, kp4, gm, blk, lcm, s, a);
@@ -584,7 +587,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     if (grads) {
       hipLaunchKernelGGL(k_adj_p5, dim3(N, (nb + kAdjGroup - 1) / kAdjGroup), blk, lm, s, a);
       hipLaunchKernelGGL(k_adj_p6, g1, blk, lc1, s, a);
-      hipLaunchKernelGGL(k_adj_p7, g, blk, l1, s, a);
+      hipLaunchKernelGGL(k_adj_p7, gr, blk, l1, s, a);
       hipLaunchKernelGGL(k_adj_pos, dim3(nb), blk, 0, s, a, nb);
       hipLaunchKernelGGL(k_adj_probe, dim3(512), blk, 0, s, a, nb);
       hipLaunchKernelGGL(k_adj_object, dim3((pb->W + kObjTile - 1) / kObjTile, (pb->H + kObjTile - 1) / kObjTile),
