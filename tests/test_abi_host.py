@@ -123,3 +123,18 @@ def test_tuning_round_trip(lib):
     assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 3))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(100, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
     assert lib.mrpie_set_tuning(128, 1, C.byref(d)) == 0  # restore the default
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 prints one JSON error line and
+    exits with status 2 before touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    line = r.stdout.strip().splitlines()[-1]
+    assert "one GPU" in json.loads(line)["error"]
+
