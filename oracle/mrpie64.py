@@ -49,7 +49,23 @@ listed in the design notes):
           |Psi_p|^2); gradients follow the torch convention
           dL/dRe + i dL/dIm for complex arrays; (1 - sqrt(I)/A) is taken as 0
           where A = 0.  Not in the paper (an extension of its forward model,
-          Eq. 4).
+          Eq. 4).  Far field only.
+  R-near  Eq. 2 leaves D_z general.  The near-field option is the paraxial
+          (Fresnel) transfer-function propagator D_z = F^-1 H F with
+          H(k) = exp(-i pi (k_y^2 + k_x^2) / N_F) on the signed integer
+          frequencies k of the N x N window, N_F = (N delta)^2 / (lambda z)
+          its Fresnel number; D_{-z} = F^-1 conj(H) F.  The intensities are
+          then detector pixels in real-space order.
+  R-xcb   XCORR_B (Methods, "Adam-based position refinement": the switch
+          that compares the model with the measured data) registers the
+          modelled detector amplitude A_j = sqrt(sum_p |D_z(P_p o_j)|^2)
+          (ref, taken before the modulus replacement) against the measured
+          amplitude sqrt(I_j) (mov), both real.  With mov(r) ~ ref(r + s),
+          s is the position error (truth minus estimate), the same sign as
+          XCORR_A's, so Eq. 8-9 use it unchanged.
+  R-canv  The canvas map (Results, sparse-scan figure) is the sum over
+          positions of the mode-summed probe intensity sum_p |P_p|^2 placed
+          at each position's integer box corner floor(pos + 0.5).
 """
 from __future__ import annotations
 
@@ -60,8 +76,9 @@ import numpy as np
 
 __all__ = [
     "Params", "fft2u", "ifft2u", "freq_grid", "split_position",
-    "fourier_shift", "modulus_project", "rpie_position_update", "rpie64",
-    "register64", "upsampled_window", "adam64", "loss_grad64", "forward_intensity64",
+    "fourier_shift", "fresnel_transfer", "propagate", "modulus_project",
+    "rpie_position_update", "rpie64", "register64", "upsampled_window",
+    "adam64", "loss_grad64", "forward_intensity64", "canvas64",
 ]
 
 
@@ -79,7 +96,7 @@ class Params:
     iter_offset: int = 0          # first iteration index (resume)
     probe_update_start: int = 0   # probe is updated from this iteration on
     subpixel: int = 0             # 0 = nearest-integer crop, 1 = Fourier shift
-    refine: int = 0               # XCORR_A position refinement on/off
+    refine: int = 0               # position refinement (Eq. 8-9, Alg. 1) on/off
     refine_start: int = 0
     upsample: int = 100
     xcorr_norm: int = 0           # 0 = plain cross-power (default), 1 = phase-normalised
@@ -87,6 +104,9 @@ class Params:
     adam_b1: float = 0.9
     adam_b2: float = 0.999
     adam_eps: float = 1e-8
+    xcorr_point: int = 0          # 0 = XCORR_A (o_j vs o'_j), 1 = XCORR_B (model vs measured amplitude)
+    propagator: int = 0           # 0 = far field (unitary DFT), 1 = near field (Fresnel transfer function)
+    fresnel: float = 0.0          # Fresnel number N_F of the N x N window (near field)
 
 
 # ----------------------------------------------------------------------------
@@ -123,6 +143,24 @@ def _ramp(n, f):
     return ry[:, None] * rx[None, :]
 
 
+def fresnel_transfer(n, nf):
+    """Paraxial free-space transfer function on the FFT grid (reading
+    R-near): H(k) = exp(-i pi (k_y^2 + k_x^2) / N_F), k signed integers."""
+    k = freq_grid(n)
+    return np.exp(-1j * np.pi * (k[:, None] ** 2 + k[None, :] ** 2) / nf)
+
+
+def propagate(psi, prm, inverse=False):
+    """D_z of Eq. 2 (inverse=True: D_{-z}) over the last two axes.
+
+    Far field: the unitary DFT and its inverse (reading R-dz).  Near field:
+    F^-1 H F and F^-1 conj(H) F with the Fresnel transfer function."""
+    if prm.propagator == 0:
+        return ifft2u(psi) if inverse else fft2u(psi)
+    H = fresnel_transfer(psi.shape[-1], prm.fresnel)
+    return ifft2u(fft2u(psi) * (np.conj(H) if inverse else H))
+
+
 def fourier_shift(c, f):
     """Band-limited circular shift: returns o with o(r) = c(r + f)."""
     if f[0] == 0.0 and f[1] == 0.0:
@@ -133,9 +171,9 @@ def fourier_shift(c, f):
 # ----------------------------------------------------------------------------
 # Forward model and modulus constraint
 # ----------------------------------------------------------------------------
-def forward_intensity64(P, o):
+def forward_intensity64(P, o, prm=None):
     """Mixed-state intensity, Eq. 4: I = sum_p |D_z{P_p o}|^2."""
-    Psi = fft2u(P * o[None])
+    Psi = propagate(P * o[None], prm if prm is not None else Params())
     return np.sum(np.abs(Psi) ** 2, axis=0)
 
 
@@ -161,15 +199,17 @@ def rpie_position_update(o, P, I, prm: Params, update_probe=True):
     """One M-rPIE step on a patch (Methods, Eq. 4-7).
 
     o: [N, N] object patch o_j (already shifted), P: [M, N, N] probe modes,
-    I: [N, N] intensity in FFT order.  Returns (delta_o, P_new, err_sum)
-    where delta_o is the additive object-patch update of Eq. 6, P_new the
-    probe after Eq. 5 (or P unchanged) and err_sum = sum (A - sqrt(I))^2.
+    I: [N, N] intensity (FFT order in the far field).  Returns (delta_o,
+    P_new, err_sum, A, sqrt(I)) where delta_o is the additive object-patch
+    update of Eq. 6, P_new the probe after Eq. 5 (or P unchanged), err_sum =
+    sum (A - sqrt(I))^2, and A the modelled detector amplitude before the
+    modulus replacement.
     """
     psi = P * o[None]                              # Eq. 1 / Eq. 4, per mode
-    Psi = fft2u(psi)                               # Eq. 2
+    Psi = propagate(psi, prm)                      # Eq. 2
     Psi_c, A, sqI = modulus_project(Psi, I)        # Eq. 7
     err = float(np.sum((A - sqI) ** 2))
-    psi_c = ifft2u(Psi_c)                          # D_{-z}
+    psi_c = propagate(Psi_c, prm, inverse=True)    # D_{-z}
     diff = psi_c - psi                             # psi'_{p,j} - P_p o_j
 
     # Eq. 6: object update, weighted by the (old) mode-summed probe power.
@@ -190,7 +230,7 @@ def rpie_position_update(o, P, I, prm: Params, update_probe=True):
         P_new[:, nzp] += prm.alpha_probe * upd[:, nzp] / dP[nzp]
     else:
         P_new = np.array(P, copy=True)
-    return delta_o, P_new, err
+    return delta_o, P_new, err, A, sqI
 
 
 # ----------------------------------------------------------------------------
@@ -272,7 +312,8 @@ def rpie64(O, P, pos, I, prm: Params, adam=None, record=None):
     pos: [J, 2] (y, x) box corners in pixels, I: [J, N, N] intensities in FFT
     order.  Returns dict(O, P, pos, adam, err[T]) where err[it] is the
     normalised Fourier error sum_j sum (A - sqrt(I))^2 / sum_j sum I.
-    ``record`` (optional list) receives (it, j, o, o_new) for refined steps.
+    ``record`` (optional list) receives (it, j, ref, mov) for refined
+    steps: (o, o + delta_o) for XCORR_A, (A, sqrt(I)) for XCORR_B.
     """
     O = np.array(O, dtype=np.complex128, copy=True)
     P = np.array(P, dtype=np.complex128, copy=True)
@@ -293,15 +334,18 @@ def rpie64(O, P, pos, I, prm: Params, adam=None, record=None):
                 raise ValueError(f"position {j} outside the object")
             box = (slice(n[0], n[0] + N), slice(n[1], n[1] + N))
             o = fourier_shift(O[box], f)
-            d_o, P_new, e = rpie_position_update(o, P, I[j], prm,
-                                                 update_probe=it >= prm.probe_update_start)
+            d_o, P_new, e, A, sqI = rpie_position_update(o, P, I[j], prm,
+                                                         update_probe=it >= prm.probe_update_start)
             err[t_i] += e
             P = P_new
             O[box] = O[box] + fourier_shift(d_o, -f)
             if prm.refine and it >= prm.refine_start:
-                s, _ = register64(o, o + d_o, prm.upsample, prm.xcorr_norm)
+                # XCORR_A: the patch against its own update; XCORR_B: the
+                # modelled detector amplitude against the measured one
+                ref, mov = (o, o + d_o) if prm.xcorr_point == 0 else (A, sqI)
+                s, _ = register64(ref, mov, prm.upsample, prm.xcorr_norm)
                 if record is not None:
-                    record.append((it, j, o, o + d_o))
+                    record.append((it, j, ref, mov))
                 adam64(pos[j], adam[j], s, it - prm.refine_start + 1, prm, bounds)
         err[t_i] /= Isum if Isum > 0 else 1.0
     return dict(O=O, P=P, pos=pos, adam=adam, err=err)
@@ -351,3 +395,22 @@ def loss_grad64(O, P, pos, I, subpixel=1):
             gpos[j, 0] = np.real(np.sum(np.conj(Go) * ky * Fo))
             gpos[j, 1] = np.real(np.sum(np.conj(Go) * kx * Fo))
     return L, gO, gP, gpos
+
+
+# ----------------------------------------------------------------------------
+# Canvas map (Results, sparse-scan figure)
+# ----------------------------------------------------------------------------
+def canvas64(P, pos, H, W):
+    """Canvas map (reading R-canv): sum_j sum_p |P_p|^2 placed at the box
+    of position j, on an H x W grid."""
+    P = np.asarray(P, dtype=np.complex128)
+    pos = np.asarray(pos, dtype=np.float64)
+    N = P.shape[-1]
+    Pi = np.sum(np.abs(P) ** 2, axis=0)
+    C = np.zeros((H, W))
+    for j in range(pos.shape[0]):
+        n, _ = split_position(pos[j], 0)
+        if not (0 <= n[0] <= H - N and 0 <= n[1] <= W - N):
+            raise ValueError(f"position {j} outside the object")
+        C[n[0]:n[0] + N, n[1]:n[1] + N] += Pi
+    return C

@@ -126,15 +126,29 @@ def _crop_shifted(O, p, N):
     return sfft.ifft2(sfft.fft2(c, norm="ortho") * ramp, norm="ortho")
 
 
-def simulate_patterns(rng, O, P, pos, photons, noise=True):
-    """Far-field mixed-state patterns at `pos`, scaled to a mean of `photons`
-    counts per pattern, with Poisson noise.  Returns (I float32, scale)."""
+def _fresnel_kernel(N, fresnel):
+    """Paraxial free-space transfer function of an N x N window whose Fresnel
+    number (N delta)^2 / (lambda z) is `fresnel`: exp(-i pi (ky^2 + kx^2) /
+    fresnel) on the integer FFT frequencies."""
+    q = sfft.fftfreq(N) * N
+    ph = -math.pi * (q[:, None] ** 2 + q[None, :] ** 2) / fresnel
+    return np.cos(ph) + 1j * np.sin(ph)
+
+
+def simulate_patterns(rng, O, P, pos, photons, noise=True, fresnel=None):
+    """Mixed-state patterns at `pos` (far field, FFT order; or, with a
+    Fresnel number, near field in detector-pixel order), scaled to a mean of
+    `photons` counts per pattern, with Poisson noise.  Returns (I float32,
+    scale)."""
     M, N, _ = P.shape
     J = pos.shape[0]
     I = np.empty((J, N, N), dtype=np.float64)
+    Hk = _fresnel_kernel(N, fresnel) if fresnel else None
     for j in range(J):
         o = _crop_shifted(O, pos[j], N)
         F = sfft.fft2(P * o[None], norm="ortho", axes=(-2, -1))
+        if Hk is not None:
+            F = sfft.ifft2(F * Hk[None], norm="ortho", axes=(-2, -1))
         I[j] = np.sum(F.real ** 2 + F.imag ** 2, axis=0)
     scale = photons / float(I.sum(axis=(1, 2)).mean())
     I *= scale
@@ -180,15 +194,20 @@ R2_PARAMS = dict(alpha_obj=0.1, alpha_probe=0.1, beta=1.0, gamma=1.0)
 
 
 def raster_case(seed=0, H=256, N=64, R=20.0, nside=10, step=16.0, origin=24.0,
-                jitter=2.0, photons=1e6, iterations=20, noise=True, name="raster64"):
-    """Single-mode raster workload (64^2 probe, 256^2 object, 10x10 scan)."""
+                jitter=2.0, photons=1e6, iterations=20, noise=True, name="raster64",
+                fractional=False, M=1):
+    """Raster workload (64^2 probe, 256^2 object, 10x10 scan by default).
+    `fractional` keeps the jittered positions unrounded (continuous stage
+    positions; the patterns are simulated with the Fourier shift)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     O = object_field(rng, H, H)
-    P = probe_modes(N, R, 1)
-    pos = np.floor(raster_scan(rng, nside, step, origin, jitter) + 0.5)
+    P = probe_modes(N, R, M)
+    pos = raster_scan(rng, nside, step, origin, jitter)
+    if not fractional:
+        pos = np.floor(pos + 0.5)
     I, scale = simulate_patterns(rng, O, P, pos, photons, noise)
     return _finish(name, O, P, pos, pos, I, scale, R,
-                   dict(R1_PARAMS, iterations=iterations), seed=seed)
+                   dict(R1_PARAMS, iterations=iterations, subpixel=int(fractional)), seed=seed)
 
 
 def spiral_case(seed=1, H=1024, N=256, M=3, J=1600, R=32.0, c=9.6, photons=1e7,
@@ -258,12 +277,31 @@ def batch_jobs(seed=4, njobs=64, sizes=(64, 128, 192, 256), jmin=50, jmax=900,
     return jobs
 
 
+def nearfield_case(seed=8, H=128, N=32, M=1, R=12.0, nside=6, step=12.0, origin=16.0, jitter=2.0,
+                   fresnel=40.0, diffuser_sigma=1.0, photons=1e6, noise=True, name="nearfield"):
+    """Near-field raster workload: a disc probe carrying a random diffuser
+    phase (white noise smoothed by `diffuser_sigma` px, 2 pi rms), as used
+    in near-field ptychography to give the patterns contrast; positions
+    rounded; patterns through the Fresnel transfer function of Fresnel
+    number `fresnel`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    O = object_field(rng, H, H)
+    P = probe_modes(N, R, M)
+    ph = gaussian_filter(rng.standard_normal((N, N)), diffuser_sigma, mode="wrap")
+    P = P * np.exp(2j * math.pi * ph / ph.std())[None]
+    pos = np.floor(raster_scan(rng, nside, step, origin, jitter) + 0.5)
+    I, scale = simulate_patterns(rng, O, P, pos, photons, noise, fresnel=fresnel)
+    return _finish(name, O, P, pos, pos, I, scale, R,
+                   dict(R1_PARAMS, propagator=1, fresnel=float(fresnel)), seed=seed)
+
+
 def small_case(seed, H, N, M, J, R=None, photons=1e6, subpixel=False, edges=True,
-               name="small", W=None):
+               name="small", W=None, fresnel=None):
     """Small workload for parity tests: Fermat spiral over the whole span,
     optionally with the first two positions pinned at the object corners
     (ragged / edge boxes) and optional fractional positions.  The object is
-    H x W (W = H by default)."""
+    H x W (W = H by default).  With a Fresnel number the patterns are
+    near-field (detector-pixel order)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W = H if W is None else W
     R = R if R is not None else N / 4.0
@@ -282,6 +320,8 @@ def small_case(seed, H, N, M, J, R=None, photons=1e6, subpixel=False, edges=True
     else:
         pos = np.floor(pos + 0.5)
     pos = np.clip(pos, 0, lim)
-    I, scale = simulate_patterns(rng, O, P, pos, photons, True)
-    return _finish(name, O, P, pos, pos, I, scale, R,
-                   dict(R1_PARAMS, subpixel=int(subpixel)), seed=seed)
+    I, scale = simulate_patterns(rng, O, P, pos, photons, True, fresnel=fresnel)
+    prm = dict(R1_PARAMS, subpixel=int(subpixel))
+    if fresnel:
+        prm.update(propagator=1, fresnel=float(fresnel))
+    return _finish(name, O, P, pos, pos, I, scale, R, prm, seed=seed)
