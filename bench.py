@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed instructions: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 (FMA) x 2.4 GHz (packed FP32 math, which doubles it, is not used)
+FP32_VALU_PEAK_TFS = 78.6
 
 # Per-launch HBM traffic of the plain sweep's kernels from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
@@ -69,16 +72,19 @@ def parse():
                     help="positions in the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--batch", type=int, default=8,
                     help="independent 256^2 x 3 reconstructions in the batched measurement (0 = skip)")
-    ap.add_argument("--refine-iters", type=int, default=10,
+    ap.add_argument("--refine-iters", type=int, default=50,
                     help="iterations of the position-refinement workload (0 = skip)")
     ap.add_argument("--adjoint", type=int, default=1, help="measure loss + gradient (0 = skip)")
-    ap.add_argument("--uneven", type=float, default=0.25,
-                    help="scan-length scale of the 64-job uneven batch (0 = skip, 1 = full)")
+    ap.add_argument("--uneven", type=float, default=1.0,
+                    help="scan-length scale of the 64-job uneven batch (0 = skip, 1 = the full recipe)")
+    ap.add_argument("--uneven-iters", type=int, default=20, help="iterations of the uneven batch")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the sweep launch shapes first")
     ap.add_argument("--batch-large", type=int, default=32,
                     help="also measure a batch of this many jobs (0: skip)")
     ap.add_argument("--small", type=int, default=1,
                     help="also time the 64^2 raster workload (LDS sweep vs row / column passes)")
+    ap.add_argument("--sparse-iters", type=int, default=20,
+                    help="iterations of the sparse-scan study (half the positions; 0 = skip)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -89,6 +95,35 @@ def algorithmic_bytes(N, M):
     rows = 16 * N * N * (M + 1)      # k_rows: o and P read + written
     cols = 4 * N * N                 # k_cols: I_j read
     return rows, cols
+
+
+def position_bytes(N, M):
+    """Algorithmic bytes of one position step: N^2 (16 (M + 1) + 4)."""
+    return N * N * (16 * (M + 1) + 4)
+
+
+def fft2_flops(N):
+    """Nominal flops of one N x N complex 2-D FFT: 5 N^2 log2(N^2)."""
+    import math
+    return 5.0 * N * N * math.log2(N * N)
+
+
+def hbm_roofline(kt, kernels, unit_bytes, own_bytes):
+    """Roofline of the dominant timed kernel (largest mean duration among
+    `kernels`): achieved = unit_bytes x (units one launch processes, the
+    mean grid.y of its timed launches) / its mean duration.  own_bytes(k)
+    gives that kernel's own algorithmic bytes per unit, reported beside."""
+    dom = max(kernels, key=lambda k: kt[k][0])
+    ms, n, units = kt[dom]
+    units = units if units > 0 else 1.0
+    ach = unit_bytes * units / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    own = own_bytes(dom) * units / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom, "kernel_avg_us": round(ms * 1e3, 3),
+            "launches_timed": int(n), "units_per_launch": round(units, 3),
+            "bytes_per_unit": unit_bytes, "algorithmic_bytes_per_launch": round(unit_bytes * units),
+            "kernel_own_bytes_per_launch": round(own_bytes(dom) * units),
+            "kernel_own_frac": round(own / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(w, npos):
@@ -143,19 +178,22 @@ def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_
     del g
     use_graph = el_g < el
     el_best = min(el, el_g)
-    per_launch = {"k_rows": rows_b * B, "k_cols": cols_b * B}
-    dom = max(kt, key=lambda k: kt[k][0])
-    ach = per_launch[dom] / (kt[dom][0] * 1e-3) / 1e9 if kt[dom][0] > 0 else 0.0
-    return {"jobs": B, "value": round(B * J * args.steps / el_best, 1), "unit": "positions*iter/s (aggregate)",
+    M, N = probe0.shape[0], probe0.shape[-1]
+    pb = position_bytes(N, M)
+    value = B * J * args.steps / el_best
+    # each timed launch carries the jobs of its own launch group (eager: the
+    # jobs are dealt to two streams, about B/2 per launch)
+    roof = hbm_roofline(kt, ("k_rows", "k_cols"), pb, lambda k: rows_b if k == "k_rows" else cols_b)
+    return {"jobs": B, "value": round(value, 1), "unit": "positions*iter/s (aggregate)",
             "ms_per_step": round(el_best * 1e3 / args.steps, 4),
             "launch_mode": "hip graph replay of one iteration" if use_graph else "eager launches",
             "eager": {"value": round(B * J * args.steps / el, 1), "ms_per_step": round(el * 1e3 / args.steps, 4)},
             "graph": {"value": round(B * J * args.steps / el_g, 1), "ms_per_step": round(el_g * 1e3 / args.steps, 4)},
-            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom,
-                         "kernel_avg_us": round(kt[dom][0] * 1e3, 3),
-                         "algorithmic_bytes_per_launch": per_launch[dom]},
-            "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()}}
+            "roofline": roof,
+            "path_algorithmic_GBs": round(value * pb / 1e9, 1),
+            "path_frac": round(value * pb / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
+            "kernels_units": {k: round(v[2], 2) for k, v in kt.items() if v[1]}}
 
 
 def measure_refine(api, torch, dev, args):
@@ -223,9 +261,90 @@ def measure_adjoint(api, torch, dev, obj, probe, pos, I, args):
         L, gO, gP, gp = api.adjoint(obj, probe, pos, I, subpixel=1)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / n
+    # the dominant pass (the mode column pass: 2M column-FFT halves per
+    # position) timed with dispatch events on its own stream
+    api.timing_enable(1)
+    api.adjoint(obj, probe, pos, I, subpixel=1)
+    torch.cuda.synchronize()
+    kt = api.timing_read()
+    api.timing_enable(0)
     J = pos.shape[0]
+    M, N = probe.shape[0], probe.shape[-1]
+    # whole path: (6 + 3M) 2-D FFTs of N^2 per position (loss and adjoint,
+    # exit waves recomputed), the FFT-dominated work of the gradient
+    flops_pos = (6 + 3 * M) * fft2_flops(N)
+    ms, cnt, units = kt["k_adj_p4"]
+    p4_flops = 2 * M * fft2_flops(N) / 2  # 2M column halves of a 2-D FFT
+    path_tf = flops_pos * J / el / 1e12
+    p4_tf = p4_flops * units / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"value": round(J / el, 1), "unit": "positions/s (loss + gradient)", "ms_per_eval": round(el * 1e3, 3),
-            "loss": float(L.item())}
+            "loss": float(L.item()),
+            "roofline": {"bound": "alu", "achieved": round(path_tf, 2), "peak": FP32_VALU_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": round(path_tf / FP32_VALU_PEAK_TFS, 4),
+                         "scope": "whole loss + gradient: (6 + 3M) N^2 2-D FFTs per position",
+                         "flops_per_position": flops_pos},
+            "dominant_kernel": {"kernel": "k_adj_p4", "avg_us": round(ms * 1e3, 3), "launches_timed": int(cnt),
+                                "positions_per_launch": round(units, 2),
+                                "achieved_TFs": round(p4_tf, 2),
+                                "frac": round(p4_tf / FP32_VALU_PEAK_TFS, 4),
+                                "flops_per_position": p4_flops}}
+
+
+def measure_sparse(api, torch, dev, w, args):
+    """Sparse-scan study (the paper's sparse-dataset comparison): every
+    second position of the spiral workload (half the probes), 20 iterations
+    of M-ePIE (beta = gamma = 1) and of M-rPIE (gamma = 0.1) from the same
+    start.  Each result is scaled by the complex factor that best matches
+    the true object where the canvas map (probe intensity summed over the
+    boxes) is at least half its maximum; the relative error per pixel is then
+    reported by canvas-map band, with the recovered field of view (pixels
+    whose relative error is below 0.1)."""
+    import numpy as np
+    J = w.pos0.shape[0]
+    sel = np.arange(0, J, 2)
+    pos = torch.from_numpy(np.ascontiguousarray(w.pos0[sel])).to(dev)
+    I = torch.from_numpy(np.ascontiguousarray(w.I[sel])).to(dev)
+    H, W = w.O0.shape
+    canv = api.canvas(torch.from_numpy(w.P_true).to(dev), pos, H, W).cpu().numpy().astype(np.float64)
+    cmax = canv.max()
+    Ot = w.O_true.astype(np.complex128)
+    T = args.sparse_iters
+    bands = [0.0, 0.01, 0.05, 0.1, 0.25, 0.5, 1.01]
+    out = {"workload": f"spiral256x3, every second position ({len(sel)} of {J}), {T} iterations",
+           "canvas": {"max": round(float(cmax), 1),
+                      "frac_pixels_ge_half_max": round(float(np.mean(canv >= 0.5 * cmax)), 4),
+                      "frac_pixels_lit": round(float(np.mean(canv > 0)), 4)},
+           "bands_of_canvas_max": bands}
+    for name, prm in (("M-ePIE", dict(alpha_obj=1.0, alpha_probe=1.0, beta=1.0, gamma=1.0)),
+                      ("M-rPIE", dict(w.params))):
+        prm = dict(prm)
+        prm.pop("iterations", None)
+        obj = torch.from_numpy(w.O0).to(dev)
+        probe = torch.from_numpy(w.P0).to(dev)
+        err = torch.zeros(T, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.rpie(obj, probe, pos, I, err=err, iterations=T, **prm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Or = obj.cpu().numpy().astype(np.complex128)
+        mask = canv >= 0.5 * cmax
+        c = np.vdot(Or[mask], Ot[mask]) / np.vdot(Or[mask], Or[mask])
+        rel = np.abs(c * Or - Ot) / np.abs(Ot)
+        med = []
+        for lo, hi in zip(bands[:-1], bands[1:]):
+            m = (canv >= lo * cmax) & (canv < hi * cmax)
+            med.append(round(float(np.median(rel[m])), 4) if m.any() else None)
+        good = rel < 0.1
+        out[name] = {"params": {k: prm[k] for k in ("alpha_obj", "alpha_probe", "beta", "gamma")},
+                     "final_error": round(float(err[-1].item()), 6),
+                     "median_rel_error_by_band": med,
+                     "fov_pixels_rel_error_below_0.1": int(good.sum()),
+                     "fov_frac_of_lit_pixels": round(float(good.sum() / max((canv > 0).sum(), 1)), 4),
+                     "positions_iter_per_s": round(len(sel) * T / el, 1)}
+    out["fov_ratio_rpie_over_epie"] = round(out["M-rPIE"]["fov_pixels_rel_error_below_0.1"]
+                                            / max(out["M-ePIE"]["fov_pixels_rel_error_below_0.1"], 1), 3)
+    return out
 
 
 def measure_small(api, torch, dev, args):
@@ -263,13 +382,18 @@ def measure_small(api, torch, dev, args):
 
 
 def measure_uneven(api, torch, dev, args):
-    """64 independent reconstructions of uneven N, M, J run in shared
-    launches vs the same jobs run one after another through the plain sweep."""
+    """64 independent reconstructions of uneven N, M, J (the full recipe at
+    --uneven 1: 50-900 positions, 1-5 modes, probes 64-256, 20 iterations)
+    run in shared launches vs the same jobs run one after another through
+    the plain sweep.  Both are timed as eager launches and as a replayed HIP
+    graph of one iteration (replayed `iterations` times)."""
     from synth import workloads as wl
     t0 = time.time()
-    jobs_np = wl.batch_jobs(seed=4, jscale=args.uneven, iterations=20)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    jobs_np = wl.batch_jobs(seed=4, jscale=args.uneven, iterations=args.uneven_iters, workers=workers)
     gen = time.time() - t0
-    T = 2
+    T = args.uneven_iters
+    print(f"bench: uneven batch generated in {gen:.1f} s", file=sys.stderr, flush=True)
 
     def mk():
         return [dict(obj=torch.from_numpy(j.O0).to(dev), probe=torch.from_numpy(j.P0).to(dev),
@@ -279,7 +403,7 @@ def measure_uneven(api, torch, dev, args):
     total = sum(j.pos0.shape[0] for j in jobs_np) * T
     from paper_2205_04295_amd import graph as hgraph
 
-    def timed(fn, reps=3):
+    def timed(fn, reps=2):
         # best of `reps` runs (each continues the reconstructions)
         best = float("inf")
         for _ in range(reps):
@@ -290,39 +414,50 @@ def measure_uneven(api, torch, dev, args):
             best = min(best, time.perf_counter() - t)
         return best
 
-    # batched: eager launches, then the same T iterations as one replayed graph
+    def replay_T(g):
+        for _ in range(T):
+            g.replay()
+
+    # batched: eager launches of T iterations, then one iteration captured
+    # as a graph and replayed T times
     jobs = mk()
-    for j, ws in zip(jobs, api.rpie_batched(jobs, iterations=T, **prm)):
+    for j, ws in zip(jobs, api.rpie_batched(jobs, iterations=1, **prm)):
         j["workspace"] = ws
     el_b = timed(lambda: api.rpie_batched(jobs, iterations=T, **prm))
-    g = hgraph.capture_batched(jobs, warmup=False, iterations=T, **prm)
+    g = hgraph.capture_batched(jobs, warmup=False, iterations=1, **prm)
     g.replay()
-    el_bg = timed(g.replay)
+    el_bg = timed(lambda: replay_T(g))
     del g
-    # the same jobs one after another through the plain sweep, eager and as
-    # one replayed graph
+    print("bench: uneven batch batched timings done", file=sys.stderr, flush=True)
+    # the same jobs one after another through the plain sweep
     jobs = mk()
     for j in jobs:
-        j["workspace"] = api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], iterations=T, **prm)
+        j["workspace"] = api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], iterations=1, **prm)
 
-    def seq():
+    def seq(iters):
         for j in jobs:
-            api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], workspace=j["workspace"], iterations=T, **prm)
-    el_s = timed(seq)
+            api.rpie(j["obj"], j["probe"], j["pos"], j["intens"], workspace=j["workspace"], iterations=iters, **prm)
+    el_s = timed(lambda: seq(T))
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        seq()
+        seq(1)
     g.replay()
-    el_sg = timed(g.replay)
+    el_sg = timed(lambda: replay_T(g))
     del g
-    b, sq = min(el_b, el_bg), min(el_s, el_sg)
-    return {"jobs": len(jobs_np), "scan_scale": args.uneven, "iterations": T,
-            "batched_value": round(total / b, 1), "sequential_value": round(total / sq, 1),
+    sq = min(el_s, el_sg)
+    return {"workload": "64 jobs: N ~ U{64,128,192,256}, J ~ U{50..900} x scan_scale, M ~ U{1..5}, "
+                        "Fermat spirals, R1 parameters",
+            "jobs": len(jobs_np), "scan_scale": args.uneven, "iterations": T,
+            "positions_per_iteration": total // T,
+            "value": round(total / el_bg, 1), "launch_mode": "hip graph replay of one iteration",
+            "sequential_value": round(total / sq, 1),
             "batched_eager": round(total / el_b, 1), "batched_graph": round(total / el_bg, 1),
             "sequential_eager": round(total / el_s, 1), "sequential_graph": round(total / el_sg, 1),
-            "unit": "positions*iter/s (aggregate)", "speedup": round(sq / b, 2),
-            "N_mix": sorted({int(j.P0.shape[-1]) for j in jobs_np}), "datagen_s": round(gen, 1)}
+            "unit": "positions*iter/s (aggregate)", "speedup_graph": round(sq / el_bg, 2),
+            "speedup_best": round(sq / min(el_b, el_bg), 2),
+            "N_mix": sorted({int(j.P0.shape[-1]) for j in jobs_np}), "datagen_s": round(gen, 1),
+            "datagen_workers": workers}
 
 
 def main():
@@ -394,13 +529,12 @@ def main():
     ms_per_step = el * 1e3 / args.steps
     value = J * args.steps / el
     rows_b, cols_b = algorithmic_bytes(N, M)
-    per_launch = {"k_rows": rows_b, "k_cols": cols_b}
-    # dominant kernel: largest total time per step (one launch of each per position)
-    dom = max(kt, key=lambda k: kt[k][0])
-    dom_ms = kt[dom][0]
-    achieved = per_launch[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    pb = position_bytes(N, M)
+    # dominant kernel: largest mean duration (one launch of each per position)
+    roof = hbm_roofline(kt, ("k_rows", "k_cols"), pb, lambda k: rows_b if k == "k_rows" else cols_b)
+    roof["traffic"] = counter_traffic(roof["kernel"])
     # whole-path algorithmic bandwidth (all kernels of a step)
-    path_gbs = (rows_b + cols_b) * J / (ms_per_step * 1e-3) / 1e9
+    path_gbs = pb * J / (ms_per_step * 1e-3) / 1e9
 
     batched = batched_large = None
     if args.batch > 0:
@@ -413,6 +547,7 @@ def main():
     adjoint = measure_adjoint(api, torch, dev, obj, probe, pos, I, args) if args.adjoint else None
     uneven = measure_uneven(api, torch, dev, args) if args.uneven > 0 else None
     small = measure_small(api, torch, dev, args) if args.small else None
+    sparse = measure_sparse(api, torch, dev, w, args) if args.sparse_iters > 0 else None
 
     if args.calib:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -444,13 +579,12 @@ def main():
                                "1 iteration per step, plain sequential sweep",
                    "positions": J, "N": N, "M": M, "object": list(w.O0.shape),
                    "params": {k: v for k, v in w.params.items()}},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
-                     "kernel": dom, "kernel_avg_us": round(dom_ms * 1e3, 3),
-                     "algorithmic_bytes_per_launch": per_launch[dom],
-                     "launches_timed": int(kt[dom][1])},
+        "roofline": roof,
         "kernels_us": {k: round(v[0] * 1e3, 3) for k, v in kt.items()},
+        "kernels_us_sum_per_position": round(sum(v[0] for k, v in kt.items() if k in ("k_rows", "k_cols")) * 1e3, 3),
+        "us_per_position": round(ms_per_step * 1e3 / J, 3),
         "path_algorithmic_GBs": round(path_gbs, 1),
+        "path_frac": round(path_gbs / HBM_PEAK_GBS, 4),
         "launch_mode": "hip graph replay of one iteration" if use_graph else "eager launches",
         "eager": eager,
         "graph": graph_mode,
@@ -460,6 +594,7 @@ def main():
         "adjoint": adjoint,
         "uneven_batch": uneven,
         "small_probe": small,
+        "sparse_study": sparse,
         "tuning": tuned,
         "cpu_baseline": cpu,
         "status": int(status.item()),

@@ -25,7 +25,8 @@
  *    [J][2] floats (y, x): the top-left corner of the N x N box in object
  *    pixels; diffraction intensities are [J][N][N] in FFT order (zero
  *    frequency at [0][0], no fftshift).
- *  - The far-field propagator D_z (Eq. 2) is the unitary 2-D DFT.
+ *  - The propagator D_z (Eq. 2) is the unitary 2-D DFT (far field) unless
+ *    mrpie_params.propagator selects the near-field transfer function.
  *  - Return codes: MRPIE_OK, or a negative MRPIE_E* code for errors found
  *    on the host before anything is launched (then nothing is launched and
  *    mrpie_last_error() gives a message, per calling thread).  Numerical
@@ -82,17 +83,34 @@ typedef struct {
  *          updated o'_j, Adam step per position, Eq. 8-9 and Alg. 1) in
  *          iterations >= refine_start
  *  upsample : registration upsampling factor (window ceil(1.5 up) samples)
- *  xcorr_norm: 0 = plain cross-power spectrum (the reading used for
- *          refinement: the paper follows the SciPy-ecosystem implementation
- *          of Guizar-Sicairos et al., which does not normalise), 1 =
- *          phase-normalised
- *  adam_lr, adam_b1, adam_b2, adam_eps : Adam hyper-parameters          */
+ *  xcorr_norm: 0 = plain cross-power spectrum (the default reading for
+ *          refinement: the paper says it follows the SciPy-ecosystem
+ *          implementation of Guizar-Sicairos et al., and the plain
+ *          cross-power is the one that moves the positions on the
+ *          refinement workload), 1 = phase-normalised (the paper's phrase
+ *          "weighted phase correlation" admits both)
+ *  adam_lr, adam_b1, adam_b2, adam_eps : Adam hyper-parameters
+ *  xcorr_point : where refinement compares (Methods, "Adam-based position
+ *          refinement", the XCORR_A / XCORR_B switch): 0 = XCORR_A, the
+ *          patch o_j against its update o'_j; 1 = XCORR_B, the modelled
+ *          detector amplitude sqrt(sum_p |D_z(P_p o_j)|^2) (before the
+ *          modulus replacement) against the measured sqrt(I_j)
+ *  propagator : D_z of Eq. 2.  0 = far field, the unitary 2-D DFT
+ *          (intensities in FFT order); 1 = near field, the paraxial Fresnel
+ *          transfer function D_z = F^-1 H F with H(k) = exp(-i pi (k_y^2 +
+ *          k_x^2) / fresnel) on the signed integer frequencies of the N x N
+ *          window and D_{-z} = F^-1 conj(H) F (intensities in detector-pixel
+ *          order)
+ *  fresnel : Fresnel number (N delta)^2 / (lambda z) of the N x N window,
+ *          > 0 when propagator = 1 (ignored otherwise)                    */
 typedef struct {
   float alpha_obj, alpha_probe, beta, gamma;
   int32_t iterations, iter_offset, probe_update_start;
   int32_t subpixel;
   int32_t refine, refine_start, upsample, xcorr_norm;
   float adam_lr, adam_b1, adam_b2, adam_eps;
+  int32_t xcorr_point, propagator;
+  float fresnel;
 } mrpie_params;
 
 /* Library version string (static storage). */
@@ -129,10 +147,14 @@ int mrpie_workspace_size(const mrpie_problem* pb, const mrpie_params* pr, size_t
  *  status int32, OR-ed with MRPIE_STATUS_* bits (may be NULL)
  *  ws, ws_bytes     workspace of at least mrpie_workspace_size bytes
  * The result is deterministic: the same inputs give bitwise equal outputs.
- * With refine = 1 each iteration's sweep records every position's patch
- * before and after its update, then all J pairs are registered and the
- * Adam step is taken, in order on `stream`.  No device memory is
- * allocated. */
+ * With refine = 1 each iteration's sweep records every position's pair
+ * (XCORR_A: the patch before and after its update; XCORR_B: the modelled
+ * and the measured detector amplitude), then all J pairs are registered
+ * and the Adam step is taken, in order on `stream`.  Subpixel moves,
+ * refinement and the near-field propagator run the four-launch position
+ * step; the plain far-field sweep runs two launches per position (or one
+ * workgroup per job for probes whose modes fit the LDS).  No device memory
+ * is allocated. */
 int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void* probe,
                float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);
@@ -152,49 +174,76 @@ typedef struct {
   size_t ws_bytes;
 } mrpie_job;
 
-/* Batched M-rPIE: runs mrpie_rpie's sweep (same parameters for every job;
- * refine and subpixel must be 0) on `njobs` independent reconstructions of
- * any mix of N, M, J and object size, lock-step by position: every launch
- * advances one position of every unfinished job, so one pair of launches
- * carries the work of all jobs.  Each job's object and probe match those
- * of a mrpie_rpie call on that job alone to float rounding (the single-job
- * column pass keeps its first and last FFT stages in registers; jobs that
- * run the one-workgroup LDS sweep in both are bitwise equal); the error
- * curve may differ in the summation order of its partial sums.  With two
- * or more jobs, every second job runs on an internal non-blocking stream
- * (default priority; the first such call on a device creates it and 16
- * events, kept until the process ends), forked from `stream` and joined
- * back into it before the call returns, so two lock-step launch sequences
- * share the GPU (jobs whose modes fit the LDS run their one-workgroup sweep
- * there too); while `stream` is being captured into a graph, all launches
- * stay on `stream`.  `jobs` is a HOST array read during the call. */
-int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream);
-
-/* Launch shape of the sweep's two passes, per probe size N and call class
- * (batched = 0: single-job mrpie_rpie; 1: mrpie_rpie_batched with more
- * than one job).  rows_radix / cols_radix: 4 or 8, the radix of the LDS
- * Stockham FFT stages of the row / column pass (radix 4: more threads per
- * transform, shorter latency; radix 8: fewer stages, less LDS traffic);
- * rows_threads: 256 or 512 threads per row workgroup; lds_sweep in
- * [0, 8]: a job with M <= lds_sweep whose modes fit the LDS together
- * (M N^2 <= 16384: 32^2 with up to 8 modes, 64^2 with up to 4, 128^2 with
- * 1) runs as one workgroup that keeps the probe in registers and the 2-D
- * FFT in LDS for the whole call; other jobs run the row / column passes
- * (default: 8 for N = 32, 1 for N = 64, 0 otherwise); cols_width: 1 or 4
- * adjacent detector columns per column-pass workgroup (1: shortest latency
- * for a single sweep; 4: coalesced 32-byte row segments, for batches);
- * rows_inplace: 1 runs the inverse row FFTs of multi-job launches in place
- * (half the row pass's LDS: more workgroups per CU, one more barrier per
- * FFT stage), and the column FFTs too in calls of 16 or more jobs (with
- * cols_width 4); 0 ping-pongs two buffers.  The
- * setting is process-wide host state; results do not depend on it beyond
- * float rounding.  The project's autotuner (paper_2205_04295_amd.tune) times the
- * candidates on the device and installs the fastest with mrpie_set_tuning. */
+/* Launch shape of the sweep's two passes, per probe size N, mode class of
+ * M (M = 1, 2, 3-4, 5-8) and call class (batched = 0: single-job
+ * mrpie_rpie; 1: mrpie_rpie_batched with more than one job).
+ * rows_radix / cols_radix: 4 or 8, the radix of the LDS Stockham FFT
+ * stages of the row / column pass (radix 4: more threads per transform,
+ * shorter latency; radix 8: fewer stages, less LDS traffic); rows_threads:
+ * 256 or 512 threads per row workgroup; lds_sweep in [0, 8]: a job with
+ * M <= lds_sweep whose modes fit the LDS together (M N^2 <= 16384: 32^2
+ * with up to 8 modes, 64^2 with up to 4, 128^2 with 1) runs as one
+ * workgroup that keeps the probe in registers and the 2-D FFT in LDS for
+ * the whole call; other jobs run the row / column passes (default: 8 for
+ * N = 32, 1 for N = 64, 0 otherwise); cols_width: 1 or 4 adjacent detector
+ * columns per column-pass workgroup (1: shortest latency for a single
+ * sweep; 4: coalesced 32-byte row segments, for batches); rows_inplace: 1
+ * runs the inverse row FFTs of multi-job launches in place (half the row
+ * pass's LDS: more workgroups per CU, one more barrier per FFT stage), and
+ * the column FFTs too in calls of 16 or more jobs (with cols_width 4); 0
+ * ping-pongs two buffers.  The installed setting is process-wide host
+ * state (guarded by a lock); results do not depend on it beyond float
+ * rounding.  mrpie_autotune times the candidates on the device and installs
+ * the fastest.  mrpie_set_tuning with M = 0 sets every mode class of
+ * (N, batched); mrpie_get_tuning takes M in [1, 8]. */
 typedef struct {
   int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width, rows_inplace;
 } mrpie_tuning;
-int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t);
-int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t);
+int mrpie_set_tuning(int32_t N, int32_t M, int32_t batched, const mrpie_tuning* t);
+int mrpie_get_tuning(int32_t N, int32_t M, int32_t batched, mrpie_tuning* t);
+
+/* Batched M-rPIE: runs mrpie_rpie's sweep (same parameters for every job;
+ * refine, subpixel and propagator must be 0, else MRPIE_EUNSUPPORTED) on
+ * `njobs` independent reconstructions of any mix of N, M, J and object
+ * size, lock-step by position: every launch advances one position of every
+ * unfinished job, so one pair of launches carries the work of all jobs.
+ * Each job's object and probe match those of a mrpie_rpie call on that job
+ * alone to float rounding (the single-job column pass keeps its first and
+ * last FFT stages in registers; jobs that run the one-workgroup LDS sweep in
+ * both are bitwise equal); the error curve may differ in the summation
+ * order of its partial sums.  With two or more jobs, every second job runs
+ * on an internal non-blocking stream (default priority; the first such call
+ * on a device creates it and 16 events, kept until the process ends),
+ * forked from `stream` and joined back into it before the call returns, so
+ * two lock-step launch sequences share the GPU (jobs whose modes fit the
+ * LDS run their one-workgroup sweep there too); while `stream` is being
+ * captured into a graph, all launches stay on `stream`.  `jobs` is a HOST
+ * array read during the call.  `tuning` (may be NULL) sets the launch shape
+ * of every launch of this call; NULL uses the installed tuning of each
+ * launch group's (N, mode class, batch class).  Each job brings its own
+ * workspace (jobs of different shapes need different sizes) and its own
+ * status word (jobs may share one). */
+int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, const mrpie_tuning* tuning,
+                       void* stream);
+
+/* Autotuner of the launch shapes for probe size N, the mode class of M and
+ * the batch class (batch = 1: single mrpie_rpie calls; batch > 1:
+ * mrpie_rpie_batched).  mrpie_autotune fills its workspace with `batch`
+ * synthetic problems of shape (N, M, J positions, object 3N x 3N), runs one
+ * sweep iteration with every candidate (mrpie_tuning_candidates lists them,
+ * in order) reps + 1 times on `stream` (the first run warms up), timed with
+ * HIP events, keeps each candidate's fastest timed run, installs the best
+ * candidate for that (N, mode class, batch class) as mrpie_set_tuning
+ * would, and returns it in *best (may be NULL).  cand_ms (may be NULL)
+ * receives each candidate's time in ms.  The call waits on the host for its
+ * timing events, so it may not be captured into a graph; it allocates no
+ * device memory (workspace: mrpie_autotune_workspace_size bytes, reps in
+ * [1, 100]).  mrpie_tuning_candidates writes up to `cap` candidates to
+ * `out` (may be NULL) and returns their number (or a negative error). */
+int mrpie_tuning_candidates(int32_t N, int32_t M, int32_t batched, mrpie_tuning* out, int32_t cap);
+int mrpie_autotune_workspace_size(int32_t N, int32_t M, int32_t batch, int32_t J, size_t* bytes);
+int mrpie_autotune(int32_t N, int32_t M, int32_t batch, int32_t J, int32_t reps, void* ws, size_t ws_bytes,
+                   mrpie_tuning* best, float* cand_ms, void* stream);
 
 /* Test hook: in-place unitary 2-D DFT (D_z, Eq. 2; inverse = 1 gives
  * D_{-z}) of B contiguous N x N complex64 arrays.  N in {32,64,128,192,256}. */
@@ -253,6 +302,18 @@ int mrpie_adjoint(const mrpie_problem* pb, int32_t subpixel, const void* obj, co
                   const float* intens, double* loss_out, void* grad_obj, void* grad_probe, float* grad_pos,
                   int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* Canvas map of a scan (Results, the sparse-scan figure): canvas [H][W]
+ * float32 (out, overwritten) = sum over positions j of the mode-summed
+ * probe intensity sum_p |P_p|^2 (probe [M][N][N] complex64) placed at box
+ * corner floor(pos[j] + 0.5) (pos [J][2] float32), i.e. how strongly each
+ * object pixel is illuminated.  Corners outside [0, H-N] x [0, W-N] are
+ * clamped and flagged in *status (may be NULL), as in the sweep.  Summed
+ * in double precision in scan order (deterministic).  Workspace:
+ * mrpie_canvas_workspace_size(N) bytes (the probe power map). */
+int mrpie_canvas_workspace_size(int32_t N, size_t* bytes);
+int mrpie_canvas(const mrpie_problem* pb, const void* probe, const float* pos, float* canvas, int32_t* status,
+                 void* ws, size_t ws_bytes, void* stream);
+
 /* Diagnostic kernel timing (not for use under graph capture).
  * mrpie_timing_enable(stride): from now on, every stride-th launch of each
  * timed kernel class is launched with a start / stop event pair of its own
@@ -261,11 +322,16 @@ int mrpie_adjoint(const mrpie_problem* pb, int32_t subpixel, const void* obj, co
  * 1 = sweep column pass (k_cols, k_cols1), 2 = registration column pass
  * (k_reg_cols), 3 = registration window GEMM (k_reg_gemm1), 4 = adjoint
  * modulus pass (k_adj_p4), 5 = one-workgroup LDS sweep (k_lds_sweep).
- * mrpie_timing_read(avg_ms[nkinds], count[nkinds], nkinds): waits for the
- * recorded events, returns the mean duration and number of timed launches
- * per class, and clears the record.  Host-side state, one per process. */
+ * The events are created without the system-scope fence, which would
+ * otherwise write the L2 back inside the timed dispatch.
+ * mrpie_timing_read(avg_ms[nkinds], count[nkinds], avg_units[nkinds],
+ * nkinds): waits for the recorded events, returns the mean duration, the
+ * number of timed launches and the mean grid.y of those launches (jobs per
+ * sweep pass, positions per adjoint pass, pairs per registration pass;
+ * avg_units may be NULL) per class, and clears the record.  Host-side
+ * state, one per process. */
 int mrpie_timing_enable(int32_t stride);
-int mrpie_timing_read(double* avg_ms, int64_t* count, int32_t nkinds);
+int mrpie_timing_read(double* avg_ms, int64_t* count, double* avg_units, int32_t nkinds);
 
 #ifdef __cplusplus
 }

@@ -31,12 +31,14 @@ class Params(C.Structure):
         ("subpixel", C.c_int32),
         ("refine", C.c_int32), ("refine_start", C.c_int32), ("upsample", C.c_int32), ("xcorr_norm", C.c_int32),
         ("adam_lr", C.c_float), ("adam_b1", C.c_float), ("adam_b2", C.c_float), ("adam_eps", C.c_float),
+        ("xcorr_point", C.c_int32), ("propagator", C.c_int32), ("fresnel", C.c_float),
     ]
 
 
 PARAM_DEFAULTS = dict(alpha_obj=1.0, alpha_probe=1.0, beta=1.0, gamma=1.0, iterations=1, iter_offset=0,
                       probe_update_start=0, subpixel=0, refine=0, refine_start=0, upsample=100,
-                      xcorr_norm=0, adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
+                      xcorr_norm=0, adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8,
+                      xcorr_point=0, propagator=0, fresnel=0.0)
 
 
 def make_params(**kw) -> Params:
@@ -72,9 +74,14 @@ _SIGS = {
     "mrpie_validate": (C.c_int, [C.POINTER(Problem), C.POINTER(Params)]),
     "mrpie_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_size_t)]),
     "mrpie_rpie": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
-    "mrpie_rpie_batched": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Params), _P]),
-    "mrpie_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
-    "mrpie_get_tuning": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "mrpie_rpie_batched": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Params), C.POINTER(Tuning), _P]),
+    "mrpie_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "mrpie_get_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "mrpie_tuning_candidates": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Tuning), C.c_int32]),
+    "mrpie_autotune_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                                C.POINTER(C.c_size_t)]),
+    "mrpie_autotune": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t,
+                                 C.POINTER(Tuning), C.POINTER(C.c_float), _P]),
     "mrpie_register_workspace_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "mrpie_register": (C.c_int, [C.c_int32, C.c_int32, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "mrpie_adam": (C.c_int, [C.c_int32, C.POINTER(Params), C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
@@ -84,8 +91,11 @@ _SIGS = {
                                 C.c_size_t, _P]),
     "mrpie_fft2": (C.c_int, [C.c_int32, C.c_int32, _P, C.c_int32, _P]),
     "mrpie_modulus": (C.c_int, [C.c_int32, C.c_int32, _P, _P, _P]),
+    "mrpie_canvas_workspace_size": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "mrpie_canvas": (C.c_int, [C.POINTER(Problem), _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "mrpie_timing_enable": (C.c_int, [C.c_int32]),
-    "mrpie_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "mrpie_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                     C.c_int32]),
 }
 
 _lib = None

@@ -71,12 +71,13 @@ def rpie(obj, probe, pos, intens, adam=None, err=None, status=None, workspace=No
     return workspace
 
 
-def rpie_batched(jobs, stream=None, **params):
+def rpie_batched(jobs, stream=None, tuning=None, **params):
     """Run independent M-rPIE reconstructions lock-step in shared launches.
 
     jobs: list of dicts with GPU tensors obj, probe, pos, intens and optional
-    err, status, workspace.  Keyword arguments are the shared mrpie_params.
-    Returns the list of workspaces used."""
+    err, status, workspace.  Keyword arguments are the shared mrpie_params;
+    `tuning` (a dict of mrpie_tuning fields, optional) fixes the launch shape
+    of this call.  Returns the list of workspaces used."""
     lib = _abi.load()
     prm = make_params(**params)
     arr = (_abi.Job * len(jobs))()
@@ -92,7 +93,8 @@ def rpie_batched(jobs, stream=None, **params):
                           _dev(j["pos"], torch.float32, "pos"), _dev(j["intens"], torch.float32, "intens"),
                           _opt(j.get("err"), torch.float32, "err"), _opt(j.get("status"), torch.int32, "status"),
                           _dev(ws, torch.uint8, "workspace"), C.c_size_t(ws.numel()))
-    check(lib.mrpie_rpie_batched(len(jobs), C.cast(arr, C.c_void_p), C.byref(prm), _stream(stream)))
+    tu = None if tuning is None else C.byref(_abi.Tuning(**tuning))
+    check(lib.mrpie_rpie_batched(len(jobs), C.cast(arr, C.c_void_p), C.byref(prm), tu, _stream(stream)))
     return keep
 
 
@@ -207,6 +209,22 @@ def modulus(psi, intens, stream=None):
     return psi
 
 
+def canvas(probe, pos, H, W, status=None, stream=None):
+    """Canvas map [H, W] float32: sum over positions of sum_p |P_p|^2 placed
+    at each box corner (how strongly each object pixel is illuminated)."""
+    lib = _abi.load()
+    M, N, _ = probe.shape
+    pb = Problem(H=H, W=W, N=N, M=M, J=pos.shape[0])
+    n = C.c_size_t(0)
+    check(lib.mrpie_canvas_workspace_size(N, C.byref(n)))
+    ws = torch.empty(n.value, dtype=torch.uint8, device=probe.device)
+    out = torch.empty(H, W, dtype=torch.float32, device=probe.device)
+    check(lib.mrpie_canvas(C.byref(pb), _dev(probe, torch.complex64, "probe"), _dev(pos, torch.float32, "pos"),
+                           _dev(out, torch.float32, "canvas"), _opt(status, torch.int32, "status"),
+                           _dev(ws, torch.uint8, "workspace"), C.c_size_t(ws.numel()), _stream(stream)))
+    return out
+
+
 def validate(problem: Problem, **params) -> int:
     """Host-only validation; returns the C return code (0 = OK)."""
     lib = _abi.load()
@@ -223,9 +241,11 @@ def timing_enable(stride: int):
 
 
 def timing_read():
-    """{kernel: (mean ms, launches timed)} since timing_enable; clears."""
+    """{kernel: (mean ms, launches timed, mean grid.y of the timed launches)}
+    since timing_enable; clears."""
     n = len(TIMED_KERNELS)
     avg = (C.c_double * n)()
     cnt = (C.c_int64 * n)()
-    check(_abi.load().mrpie_timing_read(avg, cnt, n))
-    return {k: (avg[i], cnt[i]) for i, k in enumerate(TIMED_KERNELS)}
+    units = (C.c_double * n)()
+    check(_abi.load().mrpie_timing_read(avg, cnt, units, n))
+    return {k: (avg[i], cnt[i], units[i]) for i, k in enumerate(TIMED_KERNELS)}

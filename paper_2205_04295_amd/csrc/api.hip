@@ -86,19 +86,21 @@ struct Timing {
   long long seen[TK_COUNT] = {};
   hipEvent_t ev[2 * kEvPairs] = {};
   int kind[kEvPairs] = {};
+  int units[kEvPairs] = {};
   int used = 0;
   bool created = false;
 };
 Timing g_timing;
 }  // namespace
 
-TimedLaunch timing_slot(int kind) {
+TimedLaunch timing_slot(int kind, int units) {
   Timing& T = g_timing;
   TimedLaunch t;
   if (T.stride <= 0) return t;
   if ((T.seen[kind]++ % T.stride) != 0 || T.used >= kEvPairs) return t;
   const int slot = T.used++;
   T.kind[slot] = kind;
+  T.units[slot] = units;
   t.start = T.ev[2 * slot];
   t.stop = T.ev[2 * slot + 1];
   return t;
@@ -188,7 +190,10 @@ int mrpie_timing_enable(int32_t stride) {
   Timing& T = g_timing;
   if (stride < 0) return fail(MRPIE_EINVAL, "stride < 0");
   if (stride > 0 && !T.created) {
-    for (int i = 0; i < 2 * kEvPairs; ++i) MRPIE_HIP(hipEventCreate(&T.ev[i]));
+    // no system-scope fence when the stop event is recorded: the fence would
+    // write the L2 back and lengthen exactly the dispatch being timed
+    for (int i = 0; i < 2 * kEvPairs; ++i)
+      MRPIE_HIP(hipEventCreateWithFlags(&T.ev[i], hipEventDisableSystemFence));
     T.created = true;
   }
   T.stride = stride;
@@ -197,18 +202,30 @@ int mrpie_timing_enable(int32_t stride) {
   return MRPIE_OK;
 }
 
-int mrpie_timing_read(double* avg_ms, int64_t* count, int32_t nkinds) {
+int mrpie_timing_read(double* avg_ms, int64_t* count, double* avg_units, int32_t nkinds) {
   Timing& T = g_timing;
   if (!avg_ms || !count || nkinds < 1) return fail(MRPIE_EINVAL, "bad arguments");
-  for (int k = 0; k < nkinds; ++k) { avg_ms[k] = 0.0; count[k] = 0; }
+  for (int k = 0; k < nkinds; ++k) {
+    avg_ms[k] = 0.0;
+    count[k] = 0;
+    if (avg_units) avg_units[k] = 0.0;
+  }
   for (int i = 0; i < T.used; ++i) {
     MRPIE_HIP(hipEventSynchronize(T.ev[2 * i + 1]));
     float ms = 0.f;
     MRPIE_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
     const int k = T.kind[i];
-    if (k < nkinds) { avg_ms[k] += ms; count[k] += 1; }
+    if (k < nkinds) {
+      avg_ms[k] += ms;
+      count[k] += 1;
+      if (avg_units) avg_units[k] += T.units[i];
+    }
   }
-  for (int k = 0; k < nkinds; ++k) if (count[k]) avg_ms[k] /= (double)count[k];
+  for (int k = 0; k < nkinds; ++k)
+    if (count[k]) {
+      avg_ms[k] /= (double)count[k];
+      if (avg_units) avg_units[k] /= (double)count[k];
+    }
   T.used = 0;
   for (int k = 0; k < TK_COUNT; ++k) T.seen[k] = 0;
   return MRPIE_OK;

@@ -202,11 +202,13 @@ enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4
 struct TimedLaunch {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-TimedLaunch timing_slot(int kind);
+// `units`: the launch's grid.y (jobs of a sweep pass, positions of an
+// adjoint pass, pairs of a registration pass), averaged per class.
+TimedLaunch timing_slot(int kind, int units);
 
 template <typename K, typename... A>
 inline void launch_k(int kind, K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
-  const TimedLaunch t = timing_slot(kind);
+  const TimedLaunch t = timing_slot(kind, (int)grid.y);
   if (t.start) hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, t.start, t.stop, 0u, args...);
   else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }

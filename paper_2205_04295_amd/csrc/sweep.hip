@@ -735,23 +735,36 @@ __global__ void k_probe_back(const LaunchArgs a) {
 // inverse row FFTs in batches (8 jobs: 45.4 against 49.7 us, 32 jobs: 140
 // against 164 us), ping-pong for a single sweep.  The
 // autotuner measures the alternatives on the device for any (N, M, batch).
-static Tuning g_tune[4][2];
-static bool g_tune_set[4][2];
+// Per (N, mode class, batch class); mode classes M = 1, 2, 3-4, 5-8 (the
+// register capacity the kernels are compiled for).
+static Tuning g_tune[5][4][2];
+static bool g_tune_set[5][4][2];
+static std::mutex g_tune_mu;
 
 static int batch_class(int nb) { return nb > 1 ? 1 : 0; }
+static int mode_index(int M) { return M <= 1 ? 0 : M <= 2 ? 1 : M <= 4 ? 2 : 3; }
 
-Tuning get_tuning(int N, int M, int nb) {
-  (void)M;
-  const int ni = n_index(N), bc = batch_class(nb);
-  if (ni >= 0 && g_tune_set[ni][bc]) return g_tune[ni][bc];
+Tuning default_tuning(int N, int nb) {
+  const int bc = batch_class(nb);
   return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1, bc ? 1 : 0};
 }
 
-void set_tuning(int N, int nb, const Tuning& t) {
+Tuning get_tuning(int N, int M, int nb) {
+  const int ni = n_index(N), mi = mode_index(M), bc = batch_class(nb);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (ni >= 0 && g_tune_set[ni][mi][bc]) return g_tune[ni][mi][bc];
+  return default_tuning(N, nb);
+}
+
+void set_tuning(int N, int M, int nb, const Tuning& t) {
   const int ni = n_index(N), bc = batch_class(nb);
   if (ni < 0) return;
-  g_tune[ni][bc] = t;
-  g_tune_set[ni][bc] = true;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int mi = 0; mi < 4; ++mi)
+    if (M <= 0 || mi == mode_index(M)) {
+      g_tune[ni][mi][bc] = t;
+      g_tune_set[ni][mi][bc] = true;
+    }
 }
 
 // ------------------------------------------------------------ host driver
@@ -795,7 +808,7 @@ struct PassGroup {
 // kernels, so a job computes the same bits whichever group and stream it is
 // dealt to.
 static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* jobs, float* const* err, int nb,
-                         int call_jobs, hipStream_t s) {
+                         int call_jobs, hipStream_t s, const Tuning* force) {
   g.a.c = c;
   g.a.njobs = nb;
   g.nb = nb;
@@ -808,7 +821,7 @@ static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* job
     maxM = std::max(maxM, jobs[b]->M);
     g.eo.p[b] = err[b];
   }
-  const Tuning tu = get_tuning(g.maxN, g.a.job[0].M, call_jobs);
+  const Tuning tu = force ? *force : get_tuning(g.maxN, maxM, call_jobs);
   const bool ip = call_jobs > 1 && tu.rows_inplace;
   const bool cip = ip && tu.cols_width == 4 && call_jobs >= kColsInplaceJobs;
   for (int b = 0; b < nb; ++b) g.lr = std::max(g.lr, rows_lds(g.a.job[b].N, g.a.job[b].M, ip));
@@ -854,7 +867,7 @@ static void launch_tick(const PassGroup& g, const Common& c, int t) {
 // fill it (measured at 256^2 x 3: 8 jobs 198k -> 219k, 32 jobs 266k -> 287k
 // positions x iterations / s; four streams gained less than two).
 static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s,
-                      hipStream_t s2) {
+                      hipStream_t s2, const Tuning* force) {
   const int ns = s2 ? 2 : 1;
   std::vector<PassGroup> groups;
   for (int k = 0; k < ns; ++k) {
@@ -868,7 +881,7 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
     for (int c0 = 0; c0 < n; c0 += kMaxJobsPerLaunch) {
       groups.emplace_back();
       const int rc = prepare_group(groups.back(), c, js.data() + c0, es.data() + c0,
-                                   std::min(kMaxJobsPerLaunch, n - c0), njobs, k == 0 ? s : s2);
+                                   std::min(kMaxJobsPerLaunch, n - c0), njobs, k == 0 ? s : s2, force);
       if (rc) return rc;
     }
   }
@@ -896,12 +909,14 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
 // Under stream capture everything stays on `s`: a replayed graph of one
 // launch chain is faster than one of two interleaved chains (8 jobs at
 // 256^2 x 3: 204k against 146k positions x iterations / s).
-int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s) {
+int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s,
+              const Tuning* force) {
   std::vector<JobRec> lj, pj;
   std::vector<float*> le, pe;
   for (int b = 0; b < njobs; ++b) {
     const JobRec& jb = jobs[b];
-    const bool lds = jb.M <= get_tuning(jb.N, jb.M, njobs).lds_sweep && lds_sweep_fits(jb.N, jb.M);
+    const int lds_max = force ? force->lds_sweep : get_tuning(jb.N, jb.M, njobs).lds_sweep;
+    const bool lds = jb.M <= lds_max && lds_sweep_fits(jb.N, jb.M);
     (lds ? lj : pj).push_back(jb);
     (lds ? le : pe).push_back(err_out ? err_out[b] : nullptr);
   }
@@ -920,7 +935,8 @@ int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_
     MRPIE_HIP(hipStreamWaitEvent(s2, ev[0], 0));
   }
   if (!lj.empty()) rc = run_lds_sweep(c, lj.data(), (int)lj.size(), le.data(), s2 ? s2 : s);
-  if (!rc && !pj.empty()) rc = run_passes(c, pj.data(), (int)pj.size(), pe.data(), s, pj.size() >= 2 ? s2 : nullptr);
+  if (!rc && !pj.empty())
+    rc = run_passes(c, pj.data(), (int)pj.size(), pe.data(), s, pj.size() >= 2 ? s2 : nullptr, force);
   if (s2) {  // joined also after an error, so `s` never runs ahead of the side stream's work
     MRPIE_HIP(hipEventRecord(ev[1], s2));
     MRPIE_HIP(hipStreamWaitEvent(s, ev[1], 0));
@@ -963,6 +979,8 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
   la.job[0] = jb;
   launch_zero_err(la, 1, s);
   SubpixelExtra ex{pr->subpixel, nullptr, nullptr, pr->refine_start};
+  ex.xcb = pr->refine ? pr->xcorr_point : 0;
+  ex.fresnel = pr->propagator ? pr->fresnel : 0.f;
   if (!pr->refine) {
     rc = run_sweep_subpixel(c, jb, ex, 0, jb.T, true, true, s);
     if (rc) return rc;
@@ -997,6 +1015,17 @@ int run_refining_sweep(const Common& c, const JobRec& jb, const mrpie_params* pr
   return MRPIE_OK;
 }
 
+int check_tuning(const mrpie_tuning* t) {
+  if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
+  if ((t->rows_radix != 4 && t->rows_radix != 8) || (t->cols_radix != 4 && t->cols_radix != 8))
+    return fail(MRPIE_EINVAL, "radix must be 4 or 8");
+  if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
+  if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
+  if (t->cols_width != 1 && t->cols_width != 4) return fail(MRPIE_EINVAL, "cols_width must be 1 or 4");
+  if (t->rows_inplace != 0 && t->rows_inplace != 1) return fail(MRPIE_EINVAL, "rows_inplace must be 0 or 1");
+  return MRPIE_OK;
+}
+
 }  // namespace mrpie
 
 using namespace mrpie;
@@ -1027,7 +1056,11 @@ int mrpie_validate(const mrpie_problem* pb, const mrpie_params* pr) {
     if (!(pr->adam_b1 >= 0.f && pr->adam_b1 < 1.f) || !(pr->adam_b2 >= 0.f && pr->adam_b2 < 1.f))
       return fail(MRPIE_EINVAL, "Adam betas must be in [0,1)");
     if (!(pr->adam_eps > 0.f) || !finite(pr->adam_lr)) return fail(MRPIE_EINVAL, "bad Adam lr/eps");
+    if (pr->xcorr_point != 0 && pr->xcorr_point != 1) return fail(MRPIE_EINVAL, "xcorr_point must be 0 or 1");
   }
+  if (pr->propagator != 0 && pr->propagator != 1) return fail(MRPIE_EINVAL, "propagator must be 0 or 1");
+  if (pr->propagator && !(pr->fresnel > 0.f && finite(pr->fresnel)))
+    return fail(MRPIE_EINVAL, "fresnel=%g must be a finite number > 0 for the near field", pr->fresnel);
   return MRPIE_OK;
 }
 
@@ -1054,28 +1087,25 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
   JobRec jb{(float2*)obj, (float2*)probe, pos, intens, (char*)ws, status,
             pb->H, pb->W, pb->N, pb->M, pb->J, pr->iterations};
   float* eo[1] = {err_out};
-  if (!pr->subpixel && !pr->refine) return run_sweep(c, &jb, 1, eo, s);
+  if (!pr->subpixel && !pr->refine && !pr->propagator) return run_sweep(c, &jb, 1, eo, s);
   return run_refining_sweep(c, jb, pr, adam, err_out, s);
 }
 
-int mrpie_set_tuning(int32_t N, int32_t batched, const mrpie_tuning* t) {
+int mrpie_set_tuning(int32_t N, int32_t M, int32_t batched, const mrpie_tuning* t) {
   if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
-  if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
-  if ((t->rows_radix != 4 && t->rows_radix != 8) || (t->cols_radix != 4 && t->cols_radix != 8))
-    return fail(MRPIE_EINVAL, "radix must be 4 or 8");
-  if (t->rows_threads != 256 && t->rows_threads != 512) return fail(MRPIE_EINVAL, "rows_threads must be 256 or 512");
-  if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
-  if (t->cols_width != 1 && t->cols_width != 4) return fail(MRPIE_EINVAL, "cols_width must be 1 or 4");
-  if (t->rows_inplace != 0 && t->rows_inplace != 1) return fail(MRPIE_EINVAL, "rows_inplace must be 0 or 1");
-  set_tuning(N, batched ? 2 : 1,
+  if (M < 0 || M > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "M=%d not in [0, 8]", M);
+  int rc = check_tuning(t);
+  if (rc) return rc;
+  set_tuning(N, M, batched ? 2 : 1,
              Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width, t->rows_inplace});
   return MRPIE_OK;
 }
 
-int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
+int mrpie_get_tuning(int32_t N, int32_t M, int32_t batched, mrpie_tuning* t) {
   if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
+  if (M < 1 || M > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "M=%d not in [1, 8]", M);
   if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
-  const Tuning u = get_tuning(N, 1, batched ? 2 : 1);
+  const Tuning u = get_tuning(N, M, batched ? 2 : 1);
   t->rows_radix = u.rows_radix;
   t->cols_radix = u.cols_radix;
   t->rows_threads = u.rows_threads;
@@ -1085,10 +1115,18 @@ int mrpie_get_tuning(int32_t N, int32_t batched, mrpie_tuning* t) {
   return MRPIE_OK;
 }
 
-int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, void* stream) {
+int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params* pr, const mrpie_tuning* tuning,
+                       void* stream) {
   if (njobs < 0) return fail(MRPIE_EINVAL, "njobs=%d < 0", njobs);
+  if (tuning) {
+    int rc = check_tuning(tuning);
+    if (rc) return rc;
+  }
   if (njobs == 0) return MRPIE_OK;
   if (!jobs || !pr) return fail(MRPIE_EINVAL, "null jobs or params");
+  if (pr->subpixel || pr->refine || pr->propagator)
+    return fail(MRPIE_EUNSUPPORTED, "batched sweeps take integer crops, no refinement and the far field "
+                                    "(subpixel=%d refine=%d propagator=%d)", pr->subpixel, pr->refine, pr->propagator);
   std::vector<JobRec> recs((size_t)njobs);
   std::vector<float*> errs((size_t)njobs);
   for (int b = 0; b < njobs; ++b) {
@@ -1105,7 +1143,11 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
   }
   if (pr->iterations == 0) return MRPIE_OK;
   Common c{pr->alpha_obj, pr->alpha_probe, pr->beta, pr->gamma, pr->iter_offset, pr->probe_update_start};
-  return run_sweep(c, recs.data(), njobs, errs.data(), (hipStream_t)stream);
+  Tuning tu{};
+  if (tuning)
+    tu = Tuning{tuning->rows_radix, tuning->cols_radix, tuning->rows_threads, tuning->lds_sweep, tuning->cols_width,
+                tuning->rows_inplace};
+  return run_sweep(c, recs.data(), njobs, errs.data(), (hipStream_t)stream, tuning ? &tu : nullptr);
 }
 
 }  // extern "C"

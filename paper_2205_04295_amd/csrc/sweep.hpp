@@ -73,8 +73,13 @@ struct Tuning {
   int cols_width;    // 1 or 4 adjacent detector columns per column workgroup
   int rows_inplace;  // 1: multi-job row passes run their inverse FFTs in place
 };
+// The tuning of (N, mode class of M, batch class of nb jobs): the one set
+// for it, else the default.  set_tuning with M = 0 sets every mode class.
 Tuning get_tuning(int N, int M, int nb);
-void set_tuning(int N, int nb, const Tuning& t);
+void set_tuning(int N, int M, int nb, const Tuning& t);
+Tuning default_tuning(int N, int nb);
+// validates a caller's tuning (MRPIE_OK or MRPIE_EINVAL with a message)
+int check_tuning(const mrpie_tuning* t);
 
 // Subpixel / refining sweep (four launches per position): iterations
 // [it0, it0 + iters) of job `jb`; head: the first step has no previous one,
@@ -86,6 +91,8 @@ struct SubpixelExtra {
   float2* reg_ref;
   float2* reg_mov;
   int record_start;  // absolute iteration from which pairs are recorded
+  int xcb = 0;       // 1: XCORR_B pairs (model amplitude, sqrt(I)); 0: XCORR_A (o_j, o'_j)
+  float fresnel = 0.f;  // near-field Fresnel number; 0: far field
 };
 int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& ex, int it0, int iters, bool head,
                        bool tail, hipStream_t s);
@@ -108,6 +115,8 @@ int run_lds_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* 
 // `jobs` (any mix of N and M), lock-step by position: tick t performs the
 // transition (t-1 -> t) row pass and the column pass of step t of every job
 // that has one.  Writes err_out[b][T_b] when err_out[b] != nullptr.
-int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s);
+// `force` (may be null) replaces the installed tuning for every launch.
+int run_sweep(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s,
+              const Tuning* force = nullptr);
 
 }  // namespace mrpie

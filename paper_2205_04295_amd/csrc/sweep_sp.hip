@@ -21,6 +21,19 @@
 //   k_sp_cols_update (C, s)  inverse column FFTs -> psi'; probe update (Eq. 5)
 //                    and delta_o (Eq. 6) of column u; y back-move of delta_o
 //
+// Near field (Eq. 2 with a general D_z): the Fresnel transfer function
+// H(k) = exp(-i pi (k_y^2 + k_x^2) / N_F) also factors per axis, so
+// D_z = F^-1 H F is a y propagation (column FFT, h_y, inverse column FFT)
+// followed by an x propagation (the same along rows).  The exit-wave column
+// pass propagates along y, the modulus row pass propagates along x, applies
+// the modulus constraint in the detector plane and propagates back along x
+// with conj(h_x), and the update column pass propagates back along y with
+// conj(h_y): still four launches per position.
+//
+// XCORR_B (refinement against the measured data) records the modelled
+// detector amplitude A_j (before the modulus replacement) and sqrt(I_j) in
+// the modulus row pass, as the pair the registration compares.
+//
 // A move whose fraction is exactly 0 is skipped (the crop is used as is), so
 // integer positions take no Fourier round trip at all.  With refinement the
 // patch before (o_s) and after (o_s + delta_o) the update are recorded for
@@ -41,10 +54,24 @@ struct SpArgs {
   float2* reg_ref;
   float2* reg_mov;
   int record_start;
+  int xcb;        // 1: record (A_j, sqrt(I_j)) for XCORR_B, 0: (o_j, o'_j) for XCORR_A
+  float fresnel;  // Fresnel number of the N x N window; 0: far field
 };
 
 __device__ __forceinline__ bool recording(const SpArgs& a, int t) {
   return a.reg_ref && (a.c.iter_offset + t / a.jb.J) >= a.record_start;
+}
+
+// One axis of the Fresnel transfer function with the 1/N of that axis'
+// unnormalised round trip: exp(sg i pi ks^2 / N_F) / N for FFT index k
+// (signed frequency ks in fftfreq order).  The phase is reduced in double
+// precision (ks^2 / N_F reaches 10^4 rad).
+__device__ __forceinline__ float2 fresnel1(int k, float nf, float sg, int N) {
+  const int ks = k < N / 2 ? k : k - N;
+  double sn, cs;
+  sincospi((double)sg * (double)(ks * ks) / (double)nf, &sn, &cs);
+  const double s = 1.0 / (double)N;
+  return make_float2((float)(cs * s), (float)(sn * s));
 }
 
 // Box corner and fraction of position j; the fraction is 0 for a clamped
@@ -236,7 +263,7 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
   float om = 0.f, pm = 0.f;
   if (lane) {
     ((float2*)(ws + L.patch[0]))[(size_t)k * N + u] = o;
-    if (recording(a, t)) a.reg_ref[((size_t)jn * N + k) * N + u] = o;
+    if (!a.xcb && recording(a, t)) a.reg_ref[((size_t)jn * N + k) * N + u] = o;
     om = cabs2(o);
 #pragma unroll
     for (int p = 0; p < MM; ++p)
@@ -251,6 +278,17 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
     ((float*)(ws + L.pmax[0]))[u] = pm;
   }
   float2* S = fft_lds<N, false, false>(A, B, M, tw);
+  if (a.fresnel > 0.f) {  // near field: y propagation, F_y^-1 h_y F_y
+    float2* G = (S == A) ? B : A;
+    if (lane) {
+      const float2 h = fresnel1(k, a.fresnel, -1.f, N);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) G[p * N + k] = cmul(S[p * N + k], h);
+    }
+    __syncthreads();
+    S = fft_lds<N, true, false>(G, S, M, tw);
+  }
   float2* psi = (float2*)(ws + L.psi[0]);
   if (lane) {
 #pragma unroll
@@ -291,13 +329,26 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
   }
   load_twiddles<N>(tw);
   __syncthreads();
+  const bool near = a.fresnel > 0.f;
   float2* F = fft_lds<N, false, false>(A, B, M, tw);
   float2* G = (F == A) ? B : A;
-  // Eq. 7: the 2-D transform is unnormalised (N x unitary) and so is the
-  // inverse, so the scale factor carries one 1/N
+  if (near) {  // x propagation to the detector plane, F_x^-1 h_x F_x
+    if (lane) {
+      const float2 h = fresnel1(c, a.fresnel, -1.f, N);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) G[p * N + c] = cmul(F[p * N + c], h);
+    }
+    __syncthreads();
+    F = fft_lds<N, true, false>(G, F, M, tw);
+    G = (F == A) ? B : A;
+  }
+  // Eq. 7.  Far field: the 2-D transform here is unnormalised (N x unitary)
+  // and so is the inverse, so the scale factor carries one 1/N.  Near field:
+  // the propagated field is exact (each axis' round trip carries its 1/N).
   double e = 0.0, isv = 0.0;
   if (lane) {
-    const float invN = 1.0f / (float)N;
+    const float sc = near ? 1.0f : 1.0f / (float)N;
     float S = 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
@@ -305,17 +356,36 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
     const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
     const float Au = S * rs;
     const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv, 0.f));
-    const float d = Au * invN - sq;
+    const float d = Au * sc - sq;
     e = (double)d * (double)d;
     isv = (double)fmaxf(Iv, 0.f);
     if (!isfinite(S)) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
-    const float f = sq * rs * invN;
+    if (a.xcb && recording(a, t)) {  // XCORR_B pair: model amplitude, measured amplitude
+      const size_t off = ((size_t)jn * N + r) * N + c;
+      a.reg_ref[off] = make_float2(Au * sc, 0.f);
+      a.reg_mov[off] = make_float2(sq, 0.f);
+    }
+    const float f = sq * rs * sc;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) G[p * N + c] = cscale(F[p * N + c], f);
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false>(G, F, M, tw);
+  float2* H;
+  if (near) {  // back along x, F_x^-1 conj(h_x) F_x
+    float2* K = fft_lds<N, false, false>(G, F, M, tw);
+    float2* Q = (K == A) ? B : A;
+    if (lane) {
+      const float2 h = fresnel1(c, a.fresnel, 1.f, N);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) Q[p * N + c] = cmul(K[p * N + c], h);
+    }
+    __syncthreads();
+    H = fft_lds<N, true, false>(Q, K, M, tw);
+  } else {
+    H = fft_lds<N, true, false>(G, F, M, tw);
+  }
   if (lane) {
 #pragma unroll
     for (int p = 0; p < MM; ++p)
@@ -370,7 +440,21 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
   load_twiddles<N>(tw);
   float omax, pmaxv;
   block_max2(om_in, pm_in, redf, omax, pmaxv);  // (its barriers also publish A)
-  float2* R = fft_lds<N, true, false>(A, B, M, tw);
+  float2* R;
+  if (a.fresnel > 0.f) {  // near field: back along y, F_y^-1 conj(h_y) F_y
+    float2* F = fft_lds<N, false, false>(A, B, M, tw);
+    float2* G = (F == A) ? B : A;
+    if (lane) {
+      const float2 h = fresnel1(k, a.fresnel, 1.f, N);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) G[p * N + k] = cmul(F[p * N + k], h);
+    }
+    __syncthreads();
+    R = fft_lds<N, true, false>(G, F, M, tw);
+  } else {
+    R = fft_lds<N, true, false>(A, B, M, tw);
+  }
   float2* W = (R == A) ? B : A;
   const int it_abs = cm.iter_offset + t / jb.J;
   const bool upd_p = it_abs >= cm.probe_update_start;
@@ -395,7 +479,7 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
     const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
     const float go = dO != 0.f ? cm.alpha_obj / dO : 0.f;
     dlt = cscale(num, go);
-    if (recording(a, t)) a.reg_mov[((size_t)jn * N + k) * N + u] = cadd(o, dlt);
+    if (!a.xcb && recording(a, t)) a.reg_mov[((size_t)jn * N + k) * N + u] = cadd(o, dlt);
   }
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
   if (fy != 0.f) {  // y back-move of delta_o
@@ -417,7 +501,8 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
 // first loads do not wait for a kernel-argument fetch; the rest follows.
 #define MRPIE_SP_PARAMS                                                                                        \
   const float *pos, char *ws, float2 *obj, float2 *probe, int t, int mode, int J, int T, int NM, int H, int W, \
-      const float *I, int *status, float2 *reg_ref, float2 *reg_mov, int subpixel, int record_start, const Common c
+      const float *I, int *status, float2 *reg_ref, float2 *reg_mov, int subpixel, int record_start, int xcb,    \
+      float fresnel, const Common c
 #define MRPIE_SP_ARGS                                                                                  \
   SpArgs a;                                                                                            \
   a.c = c;                                                                                             \
@@ -425,7 +510,9 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
   a.subpixel = subpixel;                                                                               \
   a.reg_ref = reg_ref;                                                                                 \
   a.reg_mov = reg_mov;                                                                                 \
-  a.record_start = record_start;
+  a.record_start = record_start;                                                                       \
+  a.xcb = xcb;                                                                                         \
+  a.fresnel = fresnel;
 #define MRPIE_DISPATCH(FN, ...)              \
   switch (a.jb.N) {                          \
     case 32: FN<32>(__VA_ARGS__); break;     \
@@ -471,7 +558,7 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
   const dim3 g(N), blk(256);
 #define MRPIE_SP_LAUNCH(K, L, T_, MODE)                                                                        \
   hipLaunchKernelGGL(K, g, blk, L, s, jb.pos, jb.ws, jb.obj, jb.probe, T_, MODE, jb.J, jb.T, NM, jb.H, jb.W, jb.I, \
-                     jb.status, ex.reg_ref, ex.reg_mov, ex.subpixel, ex.record_start, c)
+                     jb.status, ex.reg_ref, ex.reg_mov, ex.subpixel, ex.record_start, ex.xcb, ex.fresnel, c)
   for (int t = t0; t < t1; ++t) {
     MRPIE_SP_LAUNCH(k_sp_rows_gather, lg, t, (t == t0 && head) ? 0 : 1);
     MRPIE_SP_LAUNCH(k_sp_cols_exit, lm, t, 0);

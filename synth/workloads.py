@@ -252,29 +252,49 @@ def gradient_subset(seed=3, H=128, N=32, M=3, R=10.0, photons=1e6):
     return _finish("grad_subset", O, P, pos, pos, I, scale, R, dict(subpixel=1), seed=seed)
 
 
+def _batch_job(seed, b, N, J, M, photons, iterations):
+    """Job b of the uneven batch, drawn from its own generator (seed, b)."""
+    rng = np.random.Generator(np.random.PCG64([seed, b]))
+    c = 0.0394 * N
+    H = int(math.ceil((2 * c * math.sqrt(J) + N + 8) / 16.0) * 16)
+    R = N / 8.0
+    O = object_field(rng, H, H)
+    P = probe_modes(N, R, M)
+    span = H - N
+    pos = np.clip(np.floor(fermat_spiral(J, c, (span / 2.0, span / 2.0)) + 0.5), 0, span)
+    I, scale = simulate_patterns(rng, O, P, pos, photons, True)
+    return _finish(f"job{b}", O, P, pos, pos, I, scale, R,
+                   dict(R1_PARAMS, iterations=iterations), seed=seed * 1000 + b)
+
+
 def batch_jobs(seed=4, njobs=64, sizes=(64, 128, 192, 256), jmin=50, jmax=900,
-               mmax=5, photons=1e6, iterations=20, jscale=1.0):
-    """Uneven batch: N ~ U{sizes}, J ~ U{jmin..jmax}, M ~ U{1..mmax}; probe
-    radius N/8, spiral step 0.0394 N (~70 % overlap), object side
-    ceil((2 c sqrt(J) + N + 8)/16)*16.  `jscale` < 1 shrinks J for tests."""
+               mmax=5, photons=1e6, iterations=20, jscale=1.0, workers=1):
+    """Uneven batch: N ~ U{sizes}, J ~ U{jmin..jmax}, M ~ U{1..mmax} (all
+    shapes drawn first from one generator), then each job from a generator
+    of its own: probe radius N/8, spiral step 0.0394 N (~70 % overlap),
+    object side ceil((2 c sqrt(J) + N + 8)/16)*16.  `jscale` < 1 shrinks J
+    for tests; `workers` > 1 simulates the jobs in that many processes (the
+    same bytes as one process)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    jobs = []
+    shapes = []
     for b in range(njobs):
         N = int(rng.choice(sizes))
         J = int(rng.integers(jmin, jmax + 1))
         M = int(rng.integers(1, mmax + 1))
-        J = max(4, int(round(J * jscale)))
-        c = 0.0394 * N
-        H = int(math.ceil((2 * c * math.sqrt(J) + N + 8) / 16.0) * 16)
-        R = N / 8.0
-        O = object_field(rng, H, H)
-        P = probe_modes(N, R, M)
-        span = H - N
-        pos = np.clip(np.floor(fermat_spiral(J, c, (span / 2.0, span / 2.0)) + 0.5), 0, span)
-        I, scale = simulate_patterns(rng, O, P, pos, photons, True)
-        jobs.append(_finish(f"job{b}", O, P, pos, pos, I, scale, R,
-                            dict(R1_PARAMS, iterations=iterations), seed=seed * 1000 + b))
-    return jobs
+        shapes.append((N, max(4, int(round(J * jscale))), M))
+    args = [(seed, b, N, J, M, photons, iterations) for b, (N, J, M) in enumerate(shapes)]
+    if workers <= 1:
+        return [_batch_job(*a) for a in args]
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    # largest jobs first, so the pool drains evenly
+    order = sorted(range(njobs), key=lambda b: -shapes[b][0] ** 2 * shapes[b][1] * shapes[b][2])
+    out = [None] * njobs
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = {b: ex.submit(_batch_job, *args[b]) for b in order}
+        for b in order:
+            out[b] = futs[b].result()
+    return out
 
 
 def nearfield_case(seed=8, H=128, N=32, M=1, R=12.0, nside=6, step=12.0, origin=16.0, jitter=2.0,

@@ -59,6 +59,10 @@ def test_validate_accepts_supported_shapes(lib):
     (Problem(256, 256, 64, 1, 10), dict(iterations=-1), _abi.MRPIE_EINVAL),
     (Problem(256, 256, 64, 1, 10), dict(alpha_obj=float("nan")), _abi.MRPIE_EINVAL),
     (Problem(256, 256, 64, 1, 10), dict(subpixel=2), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(propagator=2), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(propagator=1, fresnel=0.0), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(propagator=1, fresnel=float("inf")), _abi.MRPIE_EINVAL),
+    (Problem(256, 256, 64, 1, 10), dict(refine=1, xcorr_point=2), _abi.MRPIE_EINVAL),
 ])
 def test_validate_rejects(lib, pb, kw, code):
     assert _validate(lib, pb, **kw) == code
@@ -77,6 +81,26 @@ def test_null_arguments_rejected_before_launch(lib):
     assert rc == _abi.MRPIE_EINVAL
     assert lib.mrpie_fft2(96, 1, None, 0, None) == _abi.MRPIE_EUNSUPPORTED
     assert lib.mrpie_fft2(64, 0, None, 0, None) == 0     # empty batch: nothing to do
+
+
+def test_validate_accepts_near_field_and_xcorr_b(lib):
+    pb = Problem(256, 256, 64, 1, 10)
+    assert _validate(lib, pb, propagator=1, fresnel=40.0) == 0
+    assert _validate(lib, pb, refine=1, xcorr_point=1, propagator=1, fresnel=40.0, subpixel=1) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(subpixel=1), dict(refine=1), dict(propagator=1, fresnel=40.0)])
+def test_batched_rejects_what_it_does_not_run(lib, kw):
+    """The batched sweep takes integer crops, no refinement and the far
+    field: other settings are refused on the host, before anything is
+    launched (the job's device pointers are never touched)."""
+    fake = C.c_void_p(0x1000)
+    job = _abi.Job(Problem(256, 256, 64, 1, 10), fake, fake, fake, fake, None, None, fake, C.c_size_t(1 << 30))
+    arr = (_abi.Job * 1)(job)
+    prm = make_params(**kw)
+    rc = lib.mrpie_rpie_batched(1, C.cast(arr, C.c_void_p), C.byref(prm), None, None)
+    assert rc == _abi.MRPIE_EUNSUPPORTED
+    assert b"batched" in lib.mrpie_last_error()
 
 
 def test_workspace_too_small_rejected(lib):
@@ -103,26 +127,66 @@ def test_register_and_adam_argument_checks(lib):
     assert lib.mrpie_adam(0, C.byref(prm), 10, 10, None, None, None, 1, None) == 0
 
 
+def _fields(t):
+    return (t.rows_radix, t.cols_radix, t.rows_threads, t.lds_sweep, t.cols_width, t.rows_inplace)
+
+
 def test_tuning_round_trip(lib):
     d = _abi.Tuning()
-    assert lib.mrpie_get_tuning(128, 1, C.byref(d)) == 0
+    assert lib.mrpie_get_tuning(128, 3, 1, C.byref(d)) == 0
     assert (d.rows_radix, d.cols_radix, d.rows_threads, d.lds_sweep) == (8, 8, 256, 0)
     assert (d.cols_width, d.rows_inplace) == (4, 1)  # batch class
     d0 = _abi.Tuning()
-    assert lib.mrpie_get_tuning(128, 0, C.byref(d0)) == 0 and (d0.cols_width, d0.rows_inplace) == (1, 0)
+    assert lib.mrpie_get_tuning(128, 3, 0, C.byref(d0)) == 0 and (d0.cols_width, d0.rows_inplace) == (1, 0)
     d64 = _abi.Tuning()
-    assert lib.mrpie_get_tuning(64, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
+    assert lib.mrpie_get_tuning(64, 1, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
+    d32 = _abi.Tuning()
+    assert lib.mrpie_get_tuning(32, 5, 0, C.byref(d32)) == 0 and d32.lds_sweep == 8
+    # per mode class: setting M = 3 changes the class of M = 3-4 only
     t = _abi.Tuning(8, 4, 256, 0, 4, 1)
-    assert lib.mrpie_set_tuning(128, 1, C.byref(t)) == 0
+    assert lib.mrpie_set_tuning(128, 3, 1, C.byref(t)) == 0
+    for M, want in ((3, _fields(t)), (4, _fields(t)), (2, _fields(d)), (5, _fields(d))):
+        u = _abi.Tuning()
+        assert lib.mrpie_get_tuning(128, M, 1, C.byref(u)) == 0
+        assert _fields(u) == want, M
+    assert lib.mrpie_set_tuning(128, 0, 1, C.byref(t)) == 0   # M = 0: every mode class
     u = _abi.Tuning()
-    assert lib.mrpie_get_tuning(128, 1, C.byref(u)) == 0
-    assert (u.rows_radix, u.cols_radix, u.rows_threads, u.lds_sweep, u.cols_width, u.rows_inplace) == (8, 4, 256, 0, 4, 1)
-    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(5, 4, 256, 1, 1))) == _abi.MRPIE_EINVAL
-    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 9, 1))) == _abi.MRPIE_EINVAL
-    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 2))) == _abi.MRPIE_EINVAL
-    assert lib.mrpie_set_tuning(128, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 3))) == _abi.MRPIE_EINVAL
-    assert lib.mrpie_set_tuning(100, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
-    assert lib.mrpie_set_tuning(128, 1, C.byref(d)) == 0  # restore the default
+    assert lib.mrpie_get_tuning(128, 7, 1, C.byref(u)) == 0 and _fields(u) == _fields(t)
+    assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(5, 4, 256, 1, 1))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 9, 1))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 2))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 3))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 9, 1, C.byref(t)) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_get_tuning(128, 0, 1, C.byref(u)) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(100, 1, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
+    assert lib.mrpie_set_tuning(128, 0, 1, C.byref(d)) == 0  # restore the default
+    # N = 32 (the fifth probe size) has a table entry of its own
+    t32 = _abi.Tuning(4, 4, 512, 2, 1, 0)
+    assert lib.mrpie_set_tuning(32, 0, 0, C.byref(t32)) == 0
+    u = _abi.Tuning()
+    assert lib.mrpie_get_tuning(32, 2, 0, C.byref(u)) == 0 and _fields(u) == _fields(t32)
+    assert lib.mrpie_get_tuning(256, 2, 0, C.byref(u)) == 0 and _fields(u) == (8, 8, 256, 0, 1, 0)
+    assert lib.mrpie_set_tuning(32, 0, 0, C.byref(d32)) == 0
+
+
+def test_autotuner_candidates_and_workspace(lib):
+    """The autotuner's candidate list (the in-place option only for batches,
+    the LDS sweep only where the modes fit it) and its workspace size; the
+    timing itself needs a GPU."""
+    assert lib.mrpie_tuning_candidates(256, 3, 0, None, 0) == 16
+    assert lib.mrpie_tuning_candidates(256, 3, 1, None, 0) == 32
+    assert lib.mrpie_tuning_candidates(64, 2, 0, None, 0) == 17
+    assert lib.mrpie_tuning_candidates(64, 5, 1, None, 0) == 32
+    arr = (_abi.Tuning * 17)()
+    assert lib.mrpie_tuning_candidates(64, 2, 0, arr, 17) == 17
+    assert _fields(arr[16]) == (8, 8, 256, 8, 1, 0) and all(arr[i].rows_inplace == 0 for i in range(17))
+    assert lib.mrpie_tuning_candidates(96, 2, 0, None, 0) == _abi.MRPIE_EUNSUPPORTED
+    n = C.c_size_t(0)
+    assert lib.mrpie_autotune_workspace_size(256, 3, 2, 16, C.byref(n)) == 0
+    assert n.value >= 2 * (768 * 768 * 8 + 3 * 256 * 256 * 8 + 16 * 256 * 256 * 4)
+    assert lib.mrpie_autotune_workspace_size(256, 3, 0, 16, C.byref(n)) == _abi.MRPIE_EINVAL
+    best = _abi.Tuning()
+    assert lib.mrpie_autotune(256, 3, 1, 16, 2, None, 0, C.byref(best), None, None) == _abi.MRPIE_EWORKSPACE
 
 
 def test_bench_refuses_more_than_one_gpu():

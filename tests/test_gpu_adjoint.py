@@ -89,3 +89,42 @@ def test_loss_entry_point_and_zero_at_truth():
     L = api.loss(dev(w.O_true), dev(P), dev(w.pos0), dev(I))
     torch.cuda.synchronize()
     assert float(L.item()) < 1e-9 * float(I.sum())
+
+
+def test_gradient_across_position_chunks():
+    """300 positions: the adjoint passes take 256 positions per launch, so
+    the loss, the probe-gradient sum and the scattered object gradient
+    cross a chunk boundary."""
+    w = wl.small_case(301, 192, 64, 2, 300, subpixel=True, name="chunks")
+    O = w.O0.copy()
+    L, gO, gP, gp = gpu_grad(O, w.P0, w.pos0, w.I, 1)
+    Lo, gOo, gPo, gpo = oracle.loss_grad64(O.astype(complex), w.P0.astype(complex), w.pos0.astype(float),
+                                           w.I.astype(float), 1)
+    print(f"J=300: loss {L:.6e} vs {Lo:.6e}; gO {rel_l2(gO, gOo):.2e} gP {rel_l2(gP, gPo):.2e} "
+          f"gpos {rel_l2(gp, gpo):.2e}")
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert rel_l2(gO, gOo) < 1e-4 and rel_l2(gP, gPo) < 1e-4
+    assert rel_l2(gp, gpo) < 1e-3
+    # the positions on both sides of the chunk boundary
+    for j in (254, 255, 256, 257):
+        assert np.linalg.norm(gp[j] - gpo[j]) <= 1e-3 * max(np.linalg.norm(gpo[j]), 1e-3 * np.abs(gpo).max())
+
+
+@pytest.mark.timeout(600)
+def test_gradient_full_size_across_chunks():
+    """The 256^2 x 3 spiral workload's first 300 positions (1024^2 object)
+    with fractional offsets: loss and gradients across the 256-position
+    chunk boundary of the full-size launch shape."""
+    w = wl.spiral_case(seed=1)
+    J = 300
+    rng = np.random.default_rng(17)
+    pos = np.clip(w.pos0[:J] + rng.uniform(-0.4, 0.4, size=(J, 2)), 0, 1024 - 256).astype(np.float32)
+    O, P, I = w.O0, w.P0, w.I[:J]
+    L, gO, gP, gp = gpu_grad(O, P, pos, I, 1)
+    Lo, gOo, gPo, gpo = oracle.loss_grad64(O.astype(complex), P.astype(complex), pos.astype(float),
+                                           I.astype(float), 1)
+    print(f"256^2x3, J=300: loss {L:.6e} vs {Lo:.6e}; gO {rel_l2(gO, gOo):.2e} gP {rel_l2(gP, gPo):.2e} "
+          f"gpos {rel_l2(gp, gpo):.2e}")
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert rel_l2(gO, gOo) < 1e-4 and rel_l2(gP, gPo) < 1e-4
+    assert rel_l2(gp, gpo) < 1e-3

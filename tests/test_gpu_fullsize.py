@@ -121,3 +121,53 @@ def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine):
         moved_g, moved_o = g["pos"][0] - w.pos0[k], ref["pos"][0] - w.pos0[k]
         print(f"  Adam step gpu {moved_g} oracle {moved_o}")
         assert np.max(np.abs(moved_g - moved_o)) < 1e-4
+
+
+@pytest.fixture(scope="module")
+def spiral_oracle_run(spiral, request):
+    """The FP64 oracle on the whole workload for 20 iterations (one call per
+    iteration, the state after iterations 1 and 20 kept).  About 13 s per
+    iteration on the GPU machine's host; one line per finished iteration."""
+    cap = request.config.pluginmanager.getplugin("capturemanager")
+    w = spiral
+    prm = dict(w.params, iterations=1)
+    O, P = w.O0, w.P0
+    keep = {}
+    for it in range(20):
+        r = oracle.rpie64(O, P, w.pos0, w.I, oracle.Params(**dict(prm, iter_offset=it)))
+        O, P = r["O"], r["P"]
+        if it + 1 in (1, 20):
+            keep[it + 1] = (O.copy(), P.copy(), float(r["err"][0]))
+        with cap.global_and_fixture_disabled():
+            print(f"[oracle 1024^2 / 256^2 x 3 / 1600 positions: iteration {it + 1} of 20 done, "
+                  f"error {r['err'][0]:.5f}]", flush=True)
+    return keep
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("T,tol", [(1, 1e-4), (20, 1e-3)])
+def test_full_size_iterations_vs_oracle(spiral, spiral_oracle_run, T, tol):
+    """End to end at the full workload in the launch configuration the
+    benchmark times (one single-job call per iteration): object and probe
+    after 1 and after 20 iterations against the FP64 oracle, relative L2
+    within 1e-4 and 1e-3."""
+    w = spiral
+    prm = dict(w.params, iterations=1)
+    from paper_2205_04295_amd import api
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in
+         dict(obj=w.O0.copy(), probe=w.P0.copy(), pos=w.pos0, I=w.I).items()}
+    err = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    ws = None
+    for it in range(T):
+        ws = api.rpie(d["obj"], d["probe"], d["pos"], d["I"], err=err, status=status, workspace=ws,
+                      **dict(prm, iter_offset=it))
+    torch.cuda.synchronize()
+    O_ref, P_ref, e_ref = spiral_oracle_run[T]
+    eo = rel_l2(d["obj"].cpu().numpy(), O_ref)
+    ep = rel_l2(d["probe"].cpu().numpy(), P_ref)
+    print(f"T={T}: rel L2 object {eo:.2e} probe {ep:.2e}; error {float(err.item()):.6f} vs {e_ref:.6f}")
+    assert int(status.item()) == 0
+    assert eo < tol and ep < tol
+    assert abs(float(err.item()) - e_ref) <= 1e-3 * e_ref

@@ -1,0 +1,171 @@
+"""Near-field propagator (Eq. 2 with the Fresnel transfer function) and
+XCORR_B refinement on the GPU against the FP64 oracle, through the C ABI.
+
+The near field runs the four-launch position step (per-axis propagation
+inside the row and column passes); XCORR_B records the modelled and the
+measured detector amplitude in the modulus pass."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import workloads as wl
+
+from gpu_util import need_gpu, rel_l2, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("N,M,subpixel,nf", [(32, 1, False, 40.0), (64, 2, True, 100.0), (128, 3, False, 300.0),
+                                             (192, 1, True, 700.0), (256, 2, False, 1000.0)])
+def test_near_field_sweep_one_iteration(N, M, subpixel, nf):
+    H = 2 * N + 32
+    w = wl.small_case(200 + N, H, N, M, 9, subpixel=subpixel, name="near", fresnel=nf)
+    prm = dict(w.params, iterations=1)
+    assert prm["propagator"] == 1 and prm["fresnel"] == nf
+    g = run_gpu(w, prm)
+    o = run_oracle(w, prm)
+    eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
+    print(f"N={N} M={M} subpixel={subpixel} N_F={nf}: rel L2 object {eo:.2e} probe {ep:.2e} "
+          f"error {g['err'][0]:.6f} vs {o['err'][0]:.6f}")
+    assert g["status"] == 0
+    assert eo < 1e-4 and ep < 1e-4
+    assert abs(g["err"][0] - o["err"][0]) <= 1e-4 * o["err"][0]
+
+
+def test_near_field_twenty_iterations():
+    """The near-field raster workload (32^2 diffuser probe, 6 x 6 raster,
+    Fresnel number 40): 20 iterations against the oracle."""
+    w = wl.nearfield_case(seed=8)
+    prm = dict(w.params, iterations=20)
+    g = run_gpu(w, prm)
+    o = run_oracle(w, prm)
+    eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
+    print(f"near-field raster, 20 iterations: rel L2 object {eo:.2e} probe {ep:.2e}; "
+          f"error {g['err'][-1]:.6f} vs {o['err'][-1]:.6f}")
+    assert eo < 1e-3 and ep < 1e-3
+    assert np.allclose(g["err"], o["err"], rtol=1e-3)
+
+
+def test_far_field_unchanged_by_the_switch():
+    """propagator = 0 with a Fresnel number set is the far-field sweep."""
+    w = wl.small_case(7, 160, 64, 2, 6, name="far")
+    prm = dict(w.params, iterations=1)
+    a = run_gpu(w, dict(prm, propagator=0, fresnel=123.0))
+    b = run_gpu(w, prm)
+    assert np.array_equal(a["O"], b["O"]) and np.array_equal(a["P"], b["P"])
+
+
+def _periodic_flat(nf, seed=0):
+    """An object that repeats with the probe's period N under a constant
+    probe: the model of a box at a wrong corner is the measured pattern
+    circularly shifted by the error e (truth minus estimate), in the object
+    plane and, the propagator being a circular convolution, at the
+    detector."""
+    rng = np.random.default_rng(seed)
+    N, H = 32, 96
+    base = rng.uniform(0.5, 1.0, (N, N)) * np.exp(1j * rng.uniform(-1, 1, (N, N)))
+    O = np.tile(base, (H // N, H // N)).astype(np.complex64)
+    P = np.full((1, N, N), 1.7 + 0.4j, dtype=np.complex64)
+    true = np.array([[20., 30.], [33., 41.], [50., 17.], [40., 40.]])
+    e = np.array([[1, -2], [0, 1], [-1, -1], [2, 0]], float)
+    I, scale = wl.simulate_patterns(rng, O.astype(complex), P.astype(complex), true, 1e6, noise=False,
+                                    fresnel=nf)
+    P = (P * np.sqrt(scale)).astype(np.complex64)
+    start = (true - e).astype(np.float32)
+    return wl.Workload("periodic", O, P, true.astype(np.float32), I, O, P, start, {}), e
+
+
+@pytest.mark.parametrize("nf", [40.0, 300.0])
+def test_xcorr_b_recovers_integer_error_near_field(nf):
+    """XCORR_B on the GPU: with the updates off, every position's first Adam
+    step (t = 1) moves each axis by lr sign(e) toward the truth, as in the
+    oracle."""
+    w, e = _periodic_flat(nf)
+    prm = dict(alpha_obj=0.0, alpha_probe=0.0, beta=1.0, gamma=1.0, iterations=1, refine=1, refine_start=0,
+               xcorr_point=1, upsample=10, adam_lr=0.5, adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8,
+               propagator=1, fresnel=nf)
+    adam0 = np.zeros((4, 4), np.float32)
+    g = run_gpu(w, prm, adam=adam0)
+    o = run_oracle(w, dict(prm))
+    want = 0.5 * e / (np.abs(e) + 1e-8)
+    print("gpu moves", (g["pos"] - w.pos0).tolist(), "oracle", (o["pos"] - w.pos0).tolist())
+    assert np.max(np.abs(o["pos"] - w.pos0 - want)) < 1e-9
+    assert np.max(np.abs(g["pos"] - w.pos0 - want)) < 1e-5
+
+
+def test_xcorr_b_refinement_one_iteration_matches_oracle():
+    """A refining near-field iteration with XCORR_B on a diffuser-probe
+    workload with position errors: the sweep matches the oracle, and the
+    registered pairs (model and measured amplitude) give the oracle's peaks
+    when the same pairs are registered on the GPU."""
+    from paper_2205_04295_amd import api
+    w = wl.nearfield_case(seed=8)
+    rng = np.random.default_rng(4)
+    H = w.O0.shape[0]
+    N = w.P0.shape[-1]
+    w.pos0 = np.clip(w.pos_true + rng.normal(0, 1.5, size=w.pos_true.shape), 0, H - N).astype(np.float32)
+    prm = dict(w.params, iterations=1, subpixel=1, refine=1, xcorr_point=1, upsample=20, adam_lr=0.5,
+               adam_b1=0.9, adam_b2=0.999, adam_eps=1e-8)
+    adam0 = np.zeros((w.pos0.shape[0], 4), np.float32)
+    g = run_gpu(w, prm, adam=adam0)
+    rec = []
+    o = oracle.rpie64(w.O0, w.P0, w.pos0, w.I, oracle.Params(**prm), record=rec)
+    assert rel_l2(g["O"], o["O"]) < 1e-4 and rel_l2(g["P"], o["P"]) < 1e-4
+    ref = np.stack([r[2] for r in rec]).astype(np.complex64)
+    mov = np.stack([r[3] for r in rec]).astype(np.complex64)
+    sh, pk = api.register(torch.from_numpy(ref).cuda(), torch.from_numpy(mov).cuda(), upsample=20, norm=0)
+    torch.cuda.synchronize()
+    sh, pk = sh.cpu().numpy(), pk.cpu().numpy()
+    for b in range(len(rec)):
+        so, po = oracle.register64(ref[b].astype(complex), mov[b].astype(complex), 20, 0)
+        assert list(pk[b]) == list(po)
+        assert np.allclose(sh[b], so, atol=1e-5)
+    # the closed loop: shifts recovered from Adam's first moment agree to
+    # the window step for most positions (FP32 amplitudes may flip a peak)
+    g_gpu = g["adam"][:, :2].astype(np.float64) / (1 - np.float32(0.9))
+    g_orc = o["adam"][:, :2] / (1 - 0.9)
+    diff = np.abs(g_gpu - g_orc)
+    print("XCORR_B shifts gpu", np.round(g_gpu[:4], 3).tolist(), "oracle", np.round(g_orc[:4], 3).tolist())
+    assert np.mean(diff <= 1.01 / 20) >= 0.75
+
+
+@pytest.mark.parametrize("N,M,J,H,W", [(64, 1, 37, 200, 232), (256, 3, 300, 1024, 1024), (32, 8, 600, 96, 96)])
+def test_canvas_map_matches_oracle(N, M, J, H, W):
+    """Canvas map (sum of the probe intensity over the boxes) against the
+    oracle's, including ragged tiles (H, W not multiples of 16) and more
+    than 256 positions (the corner staging rounds)."""
+    from paper_2205_04295_amd import api
+    rng = np.random.default_rng(N + J)
+    P = (rng.standard_normal((M, N, N)) + 1j * rng.standard_normal((M, N, N))).astype(np.complex64)
+    pos = np.stack([rng.uniform(0, H - N, J), rng.uniform(0, W - N, J)], axis=1).astype(np.float32)
+    pos[0] = (0, 0)
+    pos[1] = (H - N, W - N)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c = api.canvas(torch.from_numpy(P).cuda(), torch.from_numpy(pos).cuda(), H, W, status=status)
+    torch.cuda.synchronize()
+    ref = oracle.canvas64(P.astype(complex), pos.astype(float), H, W)
+    assert int(status.item()) == 0
+    err = np.max(np.abs(c.cpu().numpy() - ref)) / ref.max()
+    print(f"canvas N={N} M={M} J={J}: max rel {err:.2e}")
+    assert err < 1e-6
+
+
+def test_canvas_map_flags_out_of_range_corners():
+    from paper_2205_04295_amd import api
+    P = torch.ones(1, 32, 32, dtype=torch.complex64, device="cuda")
+    pos = torch.tensor([[-5.0, 3.0], [10.0, 100.0]], device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c = api.canvas(P, pos, 64, 64, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) & 2
+    # clamped like the sweep: corners (0, 3) and (10, 32)
+    want = np.zeros((64, 64))
+    want[0:32, 3:35] += 1
+    want[10:42, 32:64] += 1
+    assert np.array_equal(c.cpu().numpy(), want)

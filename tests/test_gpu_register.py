@@ -72,18 +72,21 @@ def test_register_other_upsampling_and_integer_rolls(up):
     assert np.allclose(sh[3], (32, 1))   # a lag of exactly N/2 is reported as +N/2
 
 
-def test_register_rpie_patches_teacher_forced():
+@pytest.mark.parametrize("norm", [0, 1])
+def test_register_rpie_patches_teacher_forced(norm):
     """The pairs XCORR_A registers inside a refining reconstruction: a patch
-    before and after its M-rPIE update (oracle step on spiral-scan data)."""
+    before and after its M-rPIE update (oracle step on spiral-scan data),
+    with the plain cross-power (the refinement default) and phase
+    normalisation."""
     w = wl.small_case(91, 512, 256, 3, 6, subpixel=True, name="reg")
-    prm = oracle.Params(**dict(w.params, iterations=1, subpixel=1, refine=1))
+    prm = oracle.Params(**dict(w.params, iterations=1, subpixel=1, refine=1, xcorr_norm=norm))
     rec = []
     oracle.rpie64(w.O0, w.P0, w.pos0, w.I, prm, record=rec)
     ref = np.stack([r[2] for r in rec]).astype(np.complex64)
     mov = np.stack([r[3] for r in rec]).astype(np.complex64)
-    sh, pk = gpu_register(ref, mov, 100, 1)
+    sh, pk = gpu_register(ref, mov, 100, norm)
     for b in range(len(rec)):
-        so, po = oracle.register64(ref[b].astype(np.complex128), mov[b].astype(np.complex128), 100, 1)
+        so, po = oracle.register64(ref[b].astype(np.complex128), mov[b].astype(np.complex128), 100, norm)
         assert list(pk[b]) == list(po)
         assert np.allclose(sh[b], so, atol=1e-5)
 
@@ -136,3 +139,19 @@ def test_register_peaks_exact_large_windows(N, up):
         so, po = oracle.register64(ref[b].astype(np.complex128), mov[b].astype(np.complex128), up, 0)
         assert list(pk[b]) == list(po), (b, pk[b], po)
         assert np.allclose(sh[b], so, atol=1e-6)
+
+
+@pytest.mark.parametrize("norm", [0, 1])
+def test_register_across_pair_chunks(norm):
+    """300 pairs: the registration passes take 256 pairs per launch, so the
+    batch crosses a chunk boundary; every pair's peaks equal the oracle's."""
+    rng = np.random.default_rng(300 + norm)
+    B, N, up = 300, 64, 100
+    ref, mov, s = pairs_shifted(rng, B, N, noise=0.1)
+    sh, pk = gpu_register(ref, mov, up, norm)
+    bad = []
+    for b in range(B):
+        so, po = oracle.register64(ref[b].astype(np.complex128), mov[b].astype(np.complex128), up, norm)
+        if list(pk[b]) != list(po) or not np.allclose(sh[b], so, atol=1e-5):
+            bad.append((b, pk[b].tolist(), po.tolist()))
+    assert not bad, bad[:5]

@@ -261,16 +261,26 @@ def test_every_launch_shape_matches_oracle(name):
 
 
 def test_autotuner_installs_a_candidate():
+    """mrpie_autotune (through the C ABI) times every candidate and installs
+    the fastest for its (N, mode class, batch class) only."""
     from paper_2205_04295_amd import tune
-    saved, saved256 = tune.get_tuning(64, False), tune.get_tuning(256, False)
+    saved, saved256 = tune.get_tuning(64, False, M=2), tune.get_tuning(256, False, M=2)
+    other = tune.get_tuning(64, False, M=8)
     try:
         single = [c for c in tune.CANDIDATES if not c["rows_inplace"]]
         best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
         cands = single + [tune.LDS_CANDIDATE]
         assert best in cands and len(times) == len(cands)
-        assert tune.get_tuning(64, False) == best
+        assert all(t > 0 for t in times.values())
+        assert best == dict(zip(tune._KEYS, min(times, key=times.get)))
+        assert tune.get_tuning(64, False, M=2) == best
+        assert tune.get_tuning(64, False, M=8) == other   # another mode class is untouched
         best, times = tune.autotune(256, 2, batch=1, J=4, reps=1)
         assert best in single and len(times) == len(single)
+        best, times = tune.autotune(128, 3, batch=3, J=4, reps=1)
+        assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
+        assert tune.get_tuning(128, True, M=3) == best
     finally:
-        tune.set_tuning(64, False, **saved)
-        tune.set_tuning(256, False, **saved256)
+        tune.set_tuning(64, False, M=2, **saved)
+        tune.set_tuning(256, False, M=2, **saved256)
+        tune.set_tuning(128, True, M=3, **tune.get_tuning(128, True, M=1))
