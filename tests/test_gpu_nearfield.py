@@ -40,9 +40,14 @@ def test_near_field_sweep_one_iteration(N, M, subpixel, nf):
 
 def test_near_field_twenty_iterations():
     """The near-field raster workload (32^2 diffuser probe, 6 x 6 raster,
-    Fresnel number 40): 20 iterations against the oracle."""
+    Fresnel number 40): 20 iterations against the oracle with unit-step
+    weights alpha = 0.1, beta = gamma = 1 (reading R2).  Under the rPIE
+    weights (gamma = 0.1) this raster amplifies rounding chaotically in the
+    oracle itself (a 1e-7 perturbation of the start grows to 1e-1 in FP64,
+    pinned in the CPU suite), so that setting is checked step by step
+    below."""
     w = wl.nearfield_case(seed=8)
-    prm = dict(w.params, iterations=20)
+    prm = dict(w.params, iterations=20, alpha_obj=0.1, alpha_probe=0.1, beta=1.0, gamma=1.0)
     g = run_gpu(w, prm)
     o = run_oracle(w, prm)
     eo, ep = rel_l2(g["O"], o["O"]), rel_l2(g["P"], o["P"])
@@ -50,6 +55,34 @@ def test_near_field_twenty_iterations():
           f"error {g['err'][-1]:.6f} vs {o['err'][-1]:.6f}")
     assert eo < 1e-3 and ep < 1e-3
     assert np.allclose(g["err"], o["err"], rtol=1e-3)
+
+
+@pytest.mark.parametrize("k", [1, 100, 719])
+def test_near_field_rpie_step_teacher_forced(k):
+    """rPIE weights on the near-field raster: from the GPU's own state after
+    k positions (20 iterations = 720 positions), one more position on the
+    GPU and in the oracle agree to float rounding."""
+    w = wl.nearfield_case(seed=8)
+    J = w.pos0.shape[0]
+    it, j = divmod(k, J)
+    prm = dict(w.params, iterations=1)
+    O, P = w.O0, w.P0
+    for i in range(it):
+        r = run_gpu(wl.Workload(w.name, w.O_true, w.P_true, w.pos_true, w.I, O, P, w.pos0, w.params),
+                    dict(prm, iter_offset=i))
+        O, P = r["O"], r["P"]
+    if j:
+        r = run_gpu(wl.Workload(w.name, w.O_true, w.P_true, w.pos_true[:j], w.I[:j], O, P, w.pos0[:j], w.params),
+                    dict(prm, iter_offset=it))
+        O, P = r["O"], r["P"]
+    step = wl.Workload(w.name, w.O_true, w.P_true, w.pos_true[j:j + 1], w.I[j:j + 1], O, P, w.pos0[j:j + 1],
+                       w.params)
+    g = run_gpu(step, dict(prm, iter_offset=it))
+    ref = oracle.rpie64(O, P, w.pos0[j:j + 1], w.I[j:j + 1], oracle.Params(**dict(prm, iter_offset=it)))
+    eo, ep = rel_l2(g["O"], ref["O"]), rel_l2(g["P"], ref["P"])
+    dP = rel_l2(g["P"] - P, ref["P"] - P)
+    print(f"k={k}: object {eo:.2e} probe {ep:.2e} probe change {dP:.2e}")
+    assert eo < 1e-5 and ep < 1e-5 and dP < 1e-4
 
 
 def test_far_field_unchanged_by_the_switch():

@@ -691,3 +691,22 @@ def test_r1_raster_amplifies_float_rounding():
             out[name, T] = max(rel(b["O"], a["O"]), rel(b["P"], a["P"]))
     assert out["R1", 1] > 1e-3 and out["R1", 20] > 1e-2, out
     assert out["R2", 1] < 1e-6 and out["R2", 20] < 1e-4, out
+
+
+def test_near_field_raster_r1_is_chaotic_r2_is_not():
+    """The near-field raster under the rPIE weights (gamma = 0.1) amplifies a
+    1e-7 relative perturbation of the starting object to more than 1e-2
+    after 20 iterations in FP64 (so no FP32 implementation can stay within
+    1e-3 of the oracle there), while the unit-step M-ePIE weights (alpha =
+    0.1, beta = gamma = 1) keep it below 1e-5.  Evidence for the near-field
+    tolerances of the GPU tests, not a pin of the oracle's arithmetic."""
+    w = wl.nearfield_case(seed=8)
+    rng = np.random.default_rng(0)
+    O1 = w.O0.astype(complex) * (1 + 1e-7 * rng.standard_normal(w.O0.shape))
+    rel = lambda x, y: np.linalg.norm(x - y) / np.linalg.norm(y)
+    for extra, lo, hi in ((dict(), 1e-2, np.inf), (dict(alpha_obj=0.1, alpha_probe=0.1, beta=1.0, gamma=1.0), 0, 1e-5)):
+        prm = Params(**dict(w.params, iterations=20, **extra))
+        a = oracle.rpie64(w.O0, w.P0, w.pos0, w.I, prm)
+        b = oracle.rpie64(O1, w.P0, w.pos0, w.I, prm)
+        d = rel(b["O"], a["O"])
+        assert lo <= d < hi, (extra, d)
