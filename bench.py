@@ -393,7 +393,7 @@ def measure_uneven(api, torch, dev, args):
     jobs_np = wl.batch_jobs(seed=4, jscale=args.uneven, iterations=args.uneven_iters, workers=workers)
     gen = time.time() - t0
     T = args.uneven_iters
-    print(f"bench: uneven batch generated in {gen:.1f} s", file=sys.stderr, flush=True)
+    progress(f"uneven batch generated in {gen:.1f} s")
 
     def mk():
         return [dict(obj=torch.from_numpy(j.O0).to(dev), probe=torch.from_numpy(j.P0).to(dev),
@@ -428,7 +428,7 @@ def measure_uneven(api, torch, dev, args):
     g.replay()
     el_bg = timed(lambda: replay_T(g))
     del g
-    print("bench: uneven batch batched timings done", file=sys.stderr, flush=True)
+    progress("uneven batch batched timings done")
     # the same jobs one after another through the plain sweep
     jobs = mk()
     for j in jobs:
@@ -458,6 +458,10 @@ def measure_uneven(api, torch, dev, args):
             "speedup_best": round(sq / min(el_b, el_bg), 2),
             "N_mix": sorted({int(j.P0.shape[-1]) for j in jobs_np}), "datagen_s": round(gen, 1),
             "datagen_workers": workers}
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -536,6 +540,7 @@ def main():
     # whole-path algorithmic bandwidth (all kernels of a step)
     path_gbs = pb * J / (ms_per_step * 1e-3) / 1e9
 
+    progress(f"plain sweep {value:.0f} positions*iter/s")
     batched = batched_large = None
     if args.batch > 0:
         batched = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b, args.batch)
@@ -543,12 +548,18 @@ def main():
         batched_large = measure_batched(api, torch, dev, w, obj, probe, pos, I, prm, args, rows_b, cols_b,
                                         args.batch_large)
 
+    progress("batched done")
     refine = measure_refine(api, torch, dev, args) if args.refine_iters > 0 else None
+    progress("refinement done")
     adjoint = measure_adjoint(api, torch, dev, obj, probe, pos, I, args) if args.adjoint else None
+    progress("adjoint done")
     uneven = measure_uneven(api, torch, dev, args) if args.uneven > 0 else None
+    progress("uneven batch done")
     small = measure_small(api, torch, dev, args) if args.small else None
+    progress("small probe done")
     sparse = measure_sparse(api, torch, dev, w, args) if args.sparse_iters > 0 else None
 
+    progress("sparse study done")
     if args.calib:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
