@@ -159,6 +159,27 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
                float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
                void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sweep as mrpie_rpie, same arguments and results, but without a caller
+ * workspace.  Its scratch is a static device array of the library of
+ * MRPIE_NOALLOC_MAX_BYTES (16 MiB) per GPU, held by every GPU the library
+ * runs on until the process ends; its device address is looked up once per
+ * device (with that device current) on the first call there.  Problems
+ * whose mrpie_workspace_size exceeds MRPIE_NOALLOC_MAX_BYTES are refused
+ * with MRPIE_EWORKSPACE before anything is launched (256^2 probes: up to 8
+ * modes for up to 100 iterations per call, 3 modes for up to ~550).  No
+ * device memory is allocated or freed, by the library or any library it
+ * calls.  The current device must be the one `stream` belongs to.  All
+ * calls on one GPU share its array, which keeps the last call's contents
+ * (the sweep writes every scratch value before reading it): calls ordered
+ * on one stream are safe, calls that overlap on one GPU (two streams, two
+ * host threads) race and give undefined results. */
+#define MRPIE_NOALLOC_MAX_BYTES ((size_t)16 << 20)
+int mrpie_rpie_noalloc(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void* probe,
+                       float* pos, float* adam, const float* intens, float* err_out, int32_t* status,
+                       void* stream);
+
 /* One reconstruction of a batch: its shape, its arrays (device memory, as
  * for mrpie_rpie) and its own workspace (mrpie_workspace_size bytes for its
  * problem and the shared parameters). */

@@ -16,6 +16,7 @@ MRPIE_EINVAL = -1
 MRPIE_EUNSUPPORTED = -2
 MRPIE_EDEVICE = -3
 MRPIE_EWORKSPACE = -4
+NOALLOC_MAX_BYTES = 16 << 20
 STATUS_NONFINITE = 1
 STATUS_POS_CLAMPED = 2
 
@@ -74,6 +75,7 @@ _SIGS = {
     "mrpie_validate": (C.c_int, [C.POINTER(Problem), C.POINTER(Params)]),
     "mrpie_workspace_size": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_size_t)]),
     "mrpie_rpie": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "mrpie_rpie_noalloc": (C.c_int, [C.POINTER(Problem), C.POINTER(Params), _P, _P, _P, _P, _P, _P, _P, _P]),
     "mrpie_rpie_batched": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(Params), C.POINTER(Tuning), _P]),
     "mrpie_set_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "mrpie_get_tuning": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
