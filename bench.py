@@ -27,18 +27,26 @@ HBM_PEAK_GBS = 8000.0
 # x 2 (FMA) x 2.4 GHz (packed FP32 math, which doubles it, is not used)
 FP32_VALU_PEAK_TFS = 78.6
 
-# Per-launch HBM traffic of the plain sweep's kernels from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
-# counter reads for a plain 256 MiB device copy (profiles/
-# k_rows_spiral256x3_counters.md).  Valid only for the kernel sources they
-# were taken on: bench reports traffic = null when the sources differ.
+# HBM traffic of the sweep's passes from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; mean KiB per dispatch), each scaled by what the
+# counter reads for a plain 256 MiB device copy
+# (profiles/sweep_spiral256x3_trace_counters.md).  Keyed by (timed kernel
+# class, jobs per launch): 1 = the single-job kernels k_rows1 / k_cols1.
+# Valid only for the kernel sources they were taken on: bench reports
+# traffic = null when the sources differ or the launch shape was not measured.
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "8cc7357cb9fd229ce1986a8f73a3f5d117c3fb565ba5382161aea51213a3ba00",
+    "sha256": "019391aea66eca526df3f7464914b470778e889bd4c4420f96288c6b0b8782f2",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    "k_rows": {"fetch_kib": 3455.5, "write_kib": 4097.6},
-    "k_cols": {"fetch_kib": 1005.5, "write_kib": 1552.0},
+    ("k_rows", 1): {"fetch_kib": 3455.5, "write_kib": 4097.6},
+    ("k_cols", 1): {"fetch_kib": 1005.5, "write_kib": 1552.0},
+    ("k_rows", 4): {"fetch_kib": 13505.7, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3709.0, "write_kib": 6160.0},
+    ("k_rows", 16): {"fetch_kib": 54437.3, "write_kib": 65563.0},
+    ("k_cols", 16): {"fetch_kib": 14552.0, "write_kib": 24640.0},
+    ("k_rows", 32): {"fetch_kib": 108506.2, "write_kib": 131131.6},
+    ("k_cols", 32): {"fetch_kib": 28929.7, "write_kib": 49280.4},
 }
 
 
@@ -51,13 +59,13 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def counter_traffic(kernel):
-    """Scaled HBM bytes per launch of `kernel`, or None if not measured on
-    the current kernel sources."""
-    c = COUNTERS.get(kernel)
-    if c is None or COUNTERS["sha256"] != kernel_sources_sha256():
+def counter_traffic(kernel, units=1.0):
+    """Scaled HBM bytes per launch of `kernel` carrying `units` jobs, or None
+    if that launch shape was not measured on the current kernel sources."""
+    c = COUNTERS.get((kernel, int(round(units))))
+    if c is None or abs(units - round(units)) > 1e-6 or COUNTERS["sha256"] != kernel_sources_sha256():
         return None
-    return 1024.0 * (c["fetch_kib"] * COUNTERS["fetch_factor"] + c["write_kib"] * COUNTERS["write_factor"])
+    return round(1024.0 * (c["fetch_kib"] * COUNTERS["fetch_factor"] + c["write_kib"] * COUNTERS["write_factor"]))
 
 
 def parse():
@@ -184,6 +192,7 @@ def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_
     # each timed launch carries the jobs of its own launch group (eager: the
     # jobs are dealt to two streams, about B/2 per launch)
     roof = hbm_roofline(kt, ("k_rows", "k_cols"), pb, lambda k: rows_b if k == "k_rows" else cols_b)
+    roof["traffic"] = counter_traffic(roof["kernel"], roof["units_per_launch"])
     return {"jobs": B, "value": round(value, 1), "unit": "positions*iter/s (aggregate)",
             "ms_per_step": round(el_best * 1e3 / args.steps, 4),
             "launch_mode": "hip graph replay of one iteration" if use_graph else "eager launches",
@@ -536,7 +545,7 @@ def main():
     pb = position_bytes(N, M)
     # dominant kernel: largest mean duration (one launch of each per position)
     roof = hbm_roofline(kt, ("k_rows", "k_cols"), pb, lambda k: rows_b if k == "k_rows" else cols_b)
-    roof["traffic"] = counter_traffic(roof["kernel"])
+    roof["traffic"] = counter_traffic(roof["kernel"], roof["units_per_launch"])
     # whole-path algorithmic bandwidth (all kernels of a step)
     path_gbs = pb * J / (ms_per_step * 1e-3) / 1e9
 
