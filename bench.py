@@ -31,22 +31,27 @@ FP32_VALU_PEAK_TFS = 78.6
 # (FETCH_SIZE, WRITE_SIZE; mean KiB per dispatch), each scaled by what the
 # counter reads for a plain 256 MiB device copy
 # (profiles/sweep_spiral256x3_trace_counters.md).  Keyed by (timed kernel
-# class, jobs per launch): 1 = the single-job kernels k_rows1 / k_cols1.
+# class, jobs per launch): 1 = the single-job kernels k_rows1 / k_cols1;
+# k_upd / k_gat are the split row passes of batches of 16 or more jobs.
 # Valid only for the kernel sources they were taken on: bench reports
 # traffic = null when the sources differ or the launch shape was not measured.
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "019391aea66eca526df3f7464914b470778e889bd4c4420f96288c6b0b8782f2",
+    "sha256": "b7e5ebd3714a008e9917d59095f13b05914491f0a7109732eb7e0e2001625cac",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    ("k_rows", 1): {"fetch_kib": 3455.5, "write_kib": 4097.6},
-    ("k_cols", 1): {"fetch_kib": 1005.5, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13505.7, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3709.0, "write_kib": 6160.0},
-    ("k_rows", 16): {"fetch_kib": 54437.3, "write_kib": 65563.0},
-    ("k_cols", 16): {"fetch_kib": 14552.0, "write_kib": 24640.0},
-    ("k_rows", 32): {"fetch_kib": 108506.2, "write_kib": 131131.6},
-    ("k_cols", 32): {"fetch_kib": 28929.7, "write_kib": 49280.4},
+    ("k_rows", 1): {"fetch_kib": 3460.0, "write_kib": 4097.6},
+    ("k_cols", 1): {"fetch_kib": 1000.5, "write_kib": 1552.0},
+    ("k_rows", 4): {"fetch_kib": 13503.6, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3720.5, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 27353.2, "write_kib": 32780.8},
+    ("k_cols", 8): {"fetch_kib": 7315.0, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29138.0, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16715.1, "write_kib": 24832.0},
+    ("k_cols", 16): {"fetch_kib": 14557.0, "write_kib": 24640.0},
+    ("k_upd", 32): {"fetch_kib": 58194.8, "write_kib": 65730.6},
+    ("k_gat", 32): {"fetch_kib": 33356.2, "write_kib": 49664.6},
+    ("k_cols", 32): {"fetch_kib": 28934.8, "write_kib": 49295.8},
 }
 
 
@@ -134,19 +139,63 @@ def hbm_roofline(kt, kernels, unit_bytes, own_bytes):
             "kernel_own_frac": round(own / HBM_PEAK_GBS, 4)}
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, npos):
-    """The FP64 oracle timed on this host on the first `npos` positions of
-    one iteration (single-threaded numpy FFT)."""
+    """The FP64 oracle timed on this host, one thread (numpy's FFT is
+    single-threaded; BLAS is pinned to one thread): the first `npos`
+    positions of one iteration of the spiral workload (the value), plus
+    bounded samples of the other workloads' hot paths."""
+    import numpy as np
     import oracle
+    from synth import workloads as wl
     from threadpoolctl import threadpool_limits
     prm = oracle.Params(**dict(w.params, iterations=1))
+    extra = {}
     with threadpool_limits(1):
         t0 = time.perf_counter()
         oracle.rpie64(w.O0, w.P0, w.pos0[:npos], w.I[:npos], prm)
         dt = time.perf_counter() - t0
+        # the 64^2 x 1 raster workload in full (100 positions x 20 iterations)
+        r = wl.raster_case(seed=0)
+        t1 = time.perf_counter()
+        oracle.rpie64(r.O0, r.P0, r.pos0, r.I, oracle.Params(**dict(r.params, iterations=20)))
+        d1 = time.perf_counter() - t1
+        extra["raster64x1"] = {"value": round(r.pos0.shape[0] * 20 / d1, 1), "unit": "positions*iter/s",
+                               "sample": "the whole run: 100 positions x 20 iterations", "seconds": round(d1, 3)}
+        # loss + gradient (subpixel positions) on the first 64 positions
+        nj = min(64, w.pos0.shape[0])
+        t2 = time.perf_counter()
+        oracle.loss_grad64(w.O0, w.P0, w.pos0[:nj].astype(np.float64) + 0.25, w.I[:nj], subpixel=1)
+        d2 = time.perf_counter() - t2
+        extra["adjoint"] = {"value": round(nj / d2, 1), "unit": "positions/s (loss + gradient)",
+                            "sample": f"first {nj} positions of the spiral workload, quarter-pixel offsets",
+                            "seconds": round(d2, 3)}
+        # registration of 16 patch pairs at upsample 100 and 1000
+        rng = np.random.default_rng(5)
+        N = w.P0.shape[-1]
+        pairs = [(w.O0[:N, :N] * (1 + 0.01 * rng.standard_normal((N, N))), w.O0[1:N + 1, 2:N + 2])
+                 for _ in range(16)]
+        for up in (100, 1000):
+            t3 = time.perf_counter()
+            for a, b in pairs:
+                oracle.register64(a, b, up=up, norm=0)
+            d3 = time.perf_counter() - t3
+            extra[f"register_up{up}"] = {"value": round(len(pairs) / d3, 1), "unit": "pairs/s",
+                                         "sample": f"16 pairs of {N}^2 patches", "seconds": round(d3, 3)}
     return dict(value=npos / dt, unit="positions*iter/s", cores=1, kind="oracle",
                 sample=f"first {npos} of 1600 positions, 1 iteration, FP64 numpy, 1 thread",
-                seconds=round(dt, 3))
+                seconds=round(dt, 3), cpu_model=cpu_model(), threads=1, other_workloads=extra)
 
 
 def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_b, cols_b, B):
@@ -191,7 +240,11 @@ def measure_batched(api, torch, dev, w, obj0, probe0, pos0, I0, prm, args, rows_
     value = B * J * args.steps / el_best
     # each timed launch carries the jobs of its own launch group (eager: the
     # jobs are dealt to two streams, about B/2 per launch)
-    roof = hbm_roofline(kt, ("k_rows", "k_cols"), pb, lambda k: rows_b if k == "k_rows" else cols_b)
+    # the kernels' own algorithmic bytes: the row pass (fused) or the update
+    # pass (split) reads and writes o and P, the column pass reads I_j; the
+    # split gather pass moves only exchange traffic
+    own = {"k_rows": rows_b, "k_upd": rows_b, "k_cols": cols_b, "k_gat": 0}
+    roof = hbm_roofline(kt, ("k_rows", "k_cols", "k_upd", "k_gat"), pb, lambda k: own[k])
     roof["traffic"] = counter_traffic(roof["kernel"], roof["units_per_launch"])
     return {"jobs": B, "value": round(value, 1), "unit": "positions*iter/s (aggregate)",
             "ms_per_step": round(el_best * 1e3 / args.steps, 4),
@@ -506,6 +559,8 @@ def main():
         # in-place option at 8 jobs) are otherwise decided by timing noise
         tuned = {"plain": tune.autotune(N, M, batch=1, J=128, reps=4)[0],
                  "batched": tune.autotune(N, M, batch=max(2, args.batch), J=128, reps=5)[0]}
+        if args.batch_large >= 16:
+            tuned["batched_large"] = tune.autotune(N, M, batch=args.batch_large, J=64, reps=3)[0]
     ws = None
     for it in range(args.warmup):
         ws = api.rpie(obj, probe, pos, I, err=err, status=status, workspace=ws, iterations=1,

@@ -195,9 +195,9 @@ typedef struct {
   size_t ws_bytes;
 } mrpie_job;
 
-/* Launch shape of the sweep's two passes, per probe size N, mode class of
- * M (M = 1, 2, 3-4, 5-8) and call class (batched = 0: single-job
- * mrpie_rpie; 1: mrpie_rpie_batched with more than one job).
+/* Launch shape of the sweep's passes, per probe size N, mode class of M
+ * (M = 1, 2, 3-4, 5-8) and call class (batched = 0: single-job mrpie_rpie;
+ * 1: mrpie_rpie_batched with 2 to 15 jobs; 2: with 16 or more jobs).
  * rows_radix / cols_radix: 4 or 8, the radix of the LDS Stockham FFT
  * stages of the row / column pass (radix 4: more threads per transform,
  * shorter latency; radix 8: fewer stages, less LDS traffic); rows_threads:
@@ -212,13 +212,19 @@ typedef struct {
  * runs the inverse row FFTs of multi-job launches in place (half the row
  * pass's LDS: more workgroups per CU, one more barrier per FFT stage), and
  * the column FFTs too in calls of 16 or more jobs (with cols_width 4); 0
- * ping-pongs two buffers.  The installed setting is process-wide host
- * state (guarded by a lock); results do not depend on it beyond float
- * rounding.  mrpie_autotune times the candidates on the device and installs
+ * ping-pongs two buffers; rows_split: 1 makes multi-job calls run the row
+ * work of a position as two launches, the update of the previous position
+ * (inverse row FFTs, Eq. 5 and Eq. 6, the probe updated in place) and the
+ * gather of the next (exit waves, forward row FFTs), so every row of the
+ * previous spectra is transformed once and no patch copy is kept (three
+ * launches per position, less memory traffic); 0 fuses them into one row
+ * pass (two launches per position; single-job calls always fuse).  The
+ * installed setting is process-wide host state (guarded by a lock); results
+ * do not depend on it beyond float rounding.  mrpie_autotune times the candidates on the device and installs
  * the fastest.  mrpie_set_tuning with M = 0 sets every mode class of
  * (N, batched); mrpie_get_tuning takes M in [1, 8]. */
 typedef struct {
-  int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width, rows_inplace;
+  int32_t rows_radix, cols_radix, rows_threads, lds_sweep, cols_width, rows_inplace, rows_split;
 } mrpie_tuning;
 int mrpie_set_tuning(int32_t N, int32_t M, int32_t batched, const mrpie_tuning* t);
 int mrpie_get_tuning(int32_t N, int32_t M, int32_t batched, mrpie_tuning* t);
@@ -248,8 +254,8 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
                        void* stream);
 
 /* Autotuner of the launch shapes for probe size N, the mode class of M and
- * the batch class (batch = 1: single mrpie_rpie calls; batch > 1:
- * mrpie_rpie_batched).  mrpie_autotune fills its workspace with `batch`
+ * the call class of `batch` jobs (1: single mrpie_rpie calls; 2-15 and
+ * 16 or more: the two classes of mrpie_rpie_batched calls).  mrpie_autotune fills its workspace with `batch`
  * synthetic problems of shape (N, M, J positions, object 3N x 3N), runs one
  * sweep iteration with every candidate (mrpie_tuning_candidates lists them,
  * in order) reps + 1 times on `stream` (the first run warms up), timed with
@@ -342,7 +348,8 @@ int mrpie_canvas(const mrpie_problem* pb, const void* probe, const float* pos, f
  * = 0 switches timing off).  Classes: 0 = sweep row pass (k_rows, k_rows1),
  * 1 = sweep column pass (k_cols, k_cols1), 2 = registration column pass
  * (k_reg_cols), 3 = registration window GEMM (k_reg_gemm1), 4 = adjoint
- * modulus pass (k_adj_p4), 5 = one-workgroup LDS sweep (k_lds_sweep).
+ * modulus pass (k_adj_p4), 5 = one-workgroup LDS sweep (k_lds_sweep),
+ * 6 = split update pass (k_upd), 7 = split gather pass (k_gat).
  * The events are created without the system-scope fence, which would
  * otherwise write the L2 back inside the timed dispatch.
  * mrpie_timing_read(avg_ms[nkinds], count[nkinds], avg_units[nkinds],

@@ -59,7 +59,8 @@ class Job(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("rows_radix", C.c_int32), ("cols_radix", C.c_int32), ("rows_threads", C.c_int32),
-                ("lds_sweep", C.c_int32), ("cols_width", C.c_int32), ("rows_inplace", C.c_int32)]
+                ("lds_sweep", C.c_int32), ("cols_width", C.c_int32), ("rows_inplace", C.c_int32),
+                ("rows_split", C.c_int32)]
 
 
 class MrpieError(RuntimeError):

@@ -198,7 +198,9 @@ std::mutex& side_mutex();
 // launch of a timed kernel class is launched with hipExtLaunchKernelGGL and
 // a start / stop event pair, so the events carry that dispatch's own start
 // and end time on its stream; mrpie_timing_read() averages them.
-enum TimedKernel { TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_LDS = 5, TK_COUNT = 8 };
+enum TimedKernel {
+  TK_ROWS = 0, TK_COLS = 1, TK_REG = 2, TK_GEMM = 3, TK_ADJ = 4, TK_LDS = 5, TK_UPD = 6, TK_GAT = 7, TK_COUNT = 8
+};
 struct TimedLaunch {
   hipEvent_t start = nullptr, stop = nullptr;
 };

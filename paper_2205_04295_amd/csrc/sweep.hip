@@ -268,6 +268,166 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   if (i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
 
+// Split row passes for batches (three launches per position: update rows,
+// gather rows, columns).  The fused row pass above needs, in each workgroup,
+// the inverse transforms of two rows of the previous spectra whenever the
+// box moves vertically: probe row r (for the exit waves of next-box row r)
+// and box row r + dy (the object row that becomes next-box row r).  With the
+// update and the gather in launches of their own, every previous-box row is
+// inverse-transformed exactly once and the pre-update patch is read straight
+// from the object (the update is the only writer of its row), so a position
+// moves (4M + 2.5) N^2 x 8 B read and (3M + 1) N^2 x 8 B written instead of
+// about (5M + 3.5) and (3M + 2): less traffic for batches, which are bound by
+// memory traffic; one more launch, which only a single sweep's latency
+// chain would feel.  The probe is updated in place (each row by the one
+// workgroup that owns it), so no copy-back is needed at the end.
+
+// Update of step t-1 (Eq. 5, Eq. 6) for previous-box row q = blockIdx.x:
+// inverse row FFTs of its spectra, probe row q and object row q from the
+// pre-update o and P.
+template <int N, bool R4, int MM, bool IP>
+__device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
+  const int q = blockIdx.x;
+  if (t < 1 || t > total || q >= N) return;
+  const int st = t - 1, prv = st & 1;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  const size_t NN = (size_t)N * N;
+  const int tid = threadIdx.x, c = tid;
+  const bool lane = tid < N;
+  float2* tw = smem;
+  float2* bufA = tw + N;
+  float2* bufB = bufA + M * N;  // ping-pong partner (not used in place)
+  __shared__ float redf[32];
+
+  const float2* psi = (const float2*)(jb.ws + pick(L.psi, prv));
+  const int jp = st % jb.J;
+  const int ny = box_corner(jb.pos[2 * jp], jb.H - N, nullptr);  // flagged by its gather
+  const int nx = box_corner(jb.pos[2 * jp + 1], jb.W - N, nullptr);
+  float2* orow = jb.obj + (size_t)(ny + q) * jb.W + nx;
+  float2* prow = jb.probe + (size_t)q * N;
+  float2 pv[MM], Pq[MM];
+  float2 o = make_float2(0.f, 0.f);
+  float om_in = 0.f, pm_in = 0.f;
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        pv[p] = psi[p * NN + (size_t)q * N + c];
+        Pq[p] = prow[p * NN + c];
+      }
+    o = orow[c];
+    om_in = ((const float*)(jb.ws + pick(L.omax, prv)))[c];
+    pm_in = ((const float*)(jb.ws + pick(L.pmax, prv)))[c];
+  }
+  load_twiddles<N>(tw);
+  if (lane) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) bufA[p * N + c] = pv[p];
+  }
+  float omax, pmaxv;
+  block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
+  float2* res;
+  if constexpr (IP) {
+    fft_lds_inplace<N, true, R4, MM, 256>(bufA, M, tw);
+    res = bufA;
+  } else {
+    res = fft_lds<N, true, R4>(bufA, bufB, M, tw);
+  }
+  const int it_abs = cm.iter_offset + st / jb.J;
+  const bool upd_p = it_abs >= cm.probe_update_start;
+  bool bad = false;
+  if (lane) {
+    const float o2 = cabs2(o);
+    const float dP = cm.beta * omax + (1.f - cm.beta) * o2;
+    const float gP = (upd_p && dP != 0.f) ? cm.alpha_probe / dP : 0.f;
+    float ps = 0.f, Ps = 0.f;
+    float2 num = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        const float2 P = Pq[p];
+        const float2 d = csub(res[p * N + c], cmul(P, o));
+        const float2 Pn = cadd(P, cscale(cmulc(d, o), gP));
+        prow[p * NN + c] = Pn;
+        ps += cabs2(Pn);
+        num = cadd(num, cmulc(d, P));
+        Ps += cabs2(P);
+      }
+    bad |= !isfinite(ps);
+    const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
+    const float gO = dO != 0.f ? cm.alpha_obj / dO : 0.f;
+    const float2 on = cadd(o, cscale(num, gO));
+    bad |= !(isfinite(on.x) && isfinite(on.y));
+    orow[c] = on;
+  }
+  if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
+}
+
+// Gather of step t for box row r = blockIdx.x: the object row (already
+// updated by step t-1), exit waves with the updated probe row (Eq. 1, 4),
+// the row maxima the next update needs, forward row FFTs into the spectra.
+template <int N, bool R4, int MM, bool IP>
+__device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) {
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
+  const int r = blockIdx.x;
+  if (t >= total || r >= N) return;
+  const int cur = t & 1, jn = t % jb.J;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  const size_t NN = (size_t)N * N;
+  const int tid = threadIdx.x, c = tid;
+  const bool lane = tid < N;
+  float2* tw = smem;
+  float2* bufA = tw + N;
+  float2* bufB = bufA + M * N;
+  __shared__ float redf[32];
+
+  const int ny = box_corner(jb.pos[2 * jn], jb.H - N, jb.status);
+  const int nx = box_corner(jb.pos[2 * jn + 1], jb.W - N, jb.status);
+  float2 o = make_float2(0.f, 0.f);
+  float2 Pn[MM];
+  if (lane) {
+    o = jb.obj[(size_t)(ny + r) * jb.W + nx + c];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) Pn[p] = jb.probe[p * NN + (size_t)r * N + c];
+  }
+  load_twiddles<N>(tw);
+  float om = 0.f, pm_row = 0.f;
+  if (lane) {
+    om = cabs2(o);
+    float ps = 0.f;
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        ps += cabs2(Pn[p]);
+        bufA[p * N + c] = cmul(Pn[p], o);
+      }
+    pm_row = ps;
+  }
+  float pm;
+  block_max2(om, pm_row, redf, om, pm);  // (its barriers also publish bufA)
+  if (tid == 0) {
+    ((float*)(jb.ws + pick(L.omax, cur)))[r] = om;
+    ((float*)(jb.ws + pick(L.pmax, cur)))[r] = pm;
+  }
+  float2* res;
+  if constexpr (IP) {
+    fft_lds_inplace<N, false, R4, MM, 256>(bufA, M, tw);
+    res = bufA;
+  } else {
+    res = fft_lds<N, false, R4>(bufA, bufB, M, tw);
+  }
+  float2* dst = (float2*)(jb.ws + pick(L.psi, cur));
+  for (int i = tid; i < M * N; i += blockDim.x) {
+    const int p = i / N, cc = i - p * N;
+    dst[p * NN + (size_t)r * N + cc] = res[i];
+  }
+}
+
 // Column pass of step t: CW adjacent detector columns per workgroup (all
 // modes), so that every global access of the pass moves CW * 8 contiguous
 // bytes of a row (CW = 1: a single column, the shortest latency; CW = 4:
@@ -539,6 +699,32 @@ __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
   }
 }
 
+template <bool R4, int MM, bool IP>
+__global__ __launch_bounds__(512) void k_upd(const LaunchArgs a, int t) {
+  extern __shared__ float2 smem[];
+  const JobRec& jb = a.job[blockIdx.y];
+  switch (jb.N) {
+    case 32: upd_body<32, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 64: upd_body<64, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 128: upd_body<128, R4, MM, IP>(a.c, jb, t, smem); break;
+    case 192: upd_body<192, R4, MM, IP>(a.c, jb, t, smem); break;
+    default: upd_body<256, R4, MM, IP>(a.c, jb, t, smem); break;
+  }
+}
+
+template <bool R4, int MM, bool IP>
+__global__ __launch_bounds__(512) void k_gat(const LaunchArgs a, int t) {
+  extern __shared__ float2 smem[];
+  const JobRec& jb = a.job[blockIdx.y];
+  switch (jb.N) {
+    case 32: gat_body<32, R4, MM, IP>(jb, t, smem); break;
+    case 64: gat_body<64, R4, MM, IP>(jb, t, smem); break;
+    case 128: gat_body<128, R4, MM, IP>(jb, t, smem); break;
+    case 192: gat_body<192, R4, MM, IP>(jb, t, smem); break;
+    default: gat_body<256, R4, MM, IP>(jb, t, smem); break;
+  }
+}
+
 template <bool R4, int MM, int CW, bool IP>
 __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
   extern __shared__ float2 smem[];
@@ -630,6 +816,24 @@ static SweepKernel pick_cols(int mc) {
     default: return k_cols<R4, 8, CW, IP>;
   }
 }
+template <bool R4, bool IP>
+static SweepKernel pick_upd(int mc) {
+  switch (mc) {
+    case 1: return k_upd<R4, 1, IP>;
+    case 2: return k_upd<R4, 2, IP>;
+    case 4: return k_upd<R4, 4, IP>;
+    default: return k_upd<R4, 8, IP>;
+  }
+}
+template <bool R4, bool IP>
+static SweepKernel pick_gat(int mc) {
+  switch (mc) {
+    case 1: return k_gat<R4, 1, IP>;
+    case 2: return k_gat<R4, 2, IP>;
+    case 4: return k_gat<R4, 4, IP>;
+    default: return k_gat<R4, 8, IP>;
+  }
+}
 template <bool R4>
 static RowsKernel1 pick_rows1(int mc) {
   switch (mc) {
@@ -660,6 +864,16 @@ static SweepKernel rows_kernel(int radix, bool inplace, int maxM) {
   const int mc = mode_class(maxM);
   if (inplace) return radix == 8 ? pick_rows<false, true>(mc) : pick_rows<true, true>(mc);
   return radix == 8 ? pick_rows<false, false>(mc) : pick_rows<true, false>(mc);
+}
+static SweepKernel upd_kernel(int radix, bool inplace, int maxM) {
+  const int mc = mode_class(maxM);
+  if (inplace) return radix == 8 ? pick_upd<false, true>(mc) : pick_upd<true, true>(mc);
+  return radix == 8 ? pick_upd<false, false>(mc) : pick_upd<true, false>(mc);
+}
+static SweepKernel gat_kernel(int radix, bool inplace, int maxM) {
+  const int mc = mode_class(maxM);
+  if (inplace) return radix == 8 ? pick_gat<false, true>(mc) : pick_gat<true, true>(mc);
+  return radix == 8 ? pick_gat<false, false>(mc) : pick_gat<true, false>(mc);
 }
 // multi-job launches; in place only with 4 columns per workgroup
 static SweepKernel cols_kernel(int radix, int width, bool inplace, int maxM) {
@@ -737,16 +951,20 @@ __global__ void k_probe_back(const LaunchArgs a) {
 // autotuner measures the alternatives on the device for any (N, M, batch).
 // Per (N, mode class, batch class); mode classes M = 1, 2, 3-4, 5-8 (the
 // register capacity the kernels are compiled for).
-static Tuning g_tune[5][4][2];
-static bool g_tune_set[5][4][2];
+static Tuning g_tune[5][4][3];
+static bool g_tune_set[5][4][3];
 static std::mutex g_tune_mu;
 
-static int batch_class(int nb) { return nb > 1 ? 1 : 0; }
+// Call classes: a single job, batches of 2 to kLargeBatch - 1 jobs, larger
+// batches (the batch sizes where the in-place and split options pay differ).
+constexpr int kLargeBatch = 16;
+static int batch_class(int nb) { return nb <= 1 ? 0 : nb < kLargeBatch ? 1 : 2; }
+int batch_class_jobs(int cls) { return cls <= 0 ? 1 : cls == 1 ? 2 : kLargeBatch; }
 static int mode_index(int M) { return M <= 1 ? 0 : M <= 2 ? 1 : M <= 4 ? 2 : 3; }
 
 Tuning default_tuning(int N, int nb) {
   const int bc = batch_class(nb);
-  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1, bc ? 1 : 0};
+  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1, bc ? 1 : 0, bc == 2 ? 1 : 0};
 }
 
 Tuning get_tuning(int N, int M, int nb) {
@@ -770,6 +988,7 @@ void set_tuning(int N, int M, int nb, const Tuning& t) {
 // ------------------------------------------------------------ host driver
 static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 2 : 4) * M * N) * 8; }
 static size_t cols_lds(int N, int M, int cw, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * cw * M * N) * 8; }
+static size_t split_lds(int N, int M, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * M * N) * 8; }
 
 // The column pass runs in place with the row pass only in calls of this many
 // jobs or more: it doubles the workgroups per CU but adds a barrier per
@@ -796,9 +1015,10 @@ struct PassGroup {
   ErrOut eo{};
   int nb = 0, maxN = 64, maxTot = 0, width = 1;
   bool single = false;  // a single-job call: the scalar-argument kernels
-  size_t lr = 0, lc = 0;
+  bool split = false;   // update / gather / column launches per position
+  size_t lr = 0, lc = 0, lu = 0;
   dim3 rblk;
-  SweepKernel kr = nullptr, kc = nullptr;
+  SweepKernel kr = nullptr, kc = nullptr, ku = nullptr, kg = nullptr;
   RowsKernel1 kr1 = nullptr;
   ColsKernel1 kc1 = nullptr;
   hipStream_t s = nullptr;
@@ -834,6 +1054,15 @@ static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* job
     g.kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, g.a.job[0].M);
     MRPIE_HIP(ensure_lds((const void*)g.kr1, g.lr));
     MRPIE_HIP(ensure_lds((const void*)g.kc1, g.lc));
+  } else if (tu.rows_split) {
+    g.split = true;
+    for (int b = 0; b < nb; ++b) g.lu = std::max(g.lu, split_lds(g.a.job[b].N, g.a.job[b].M, ip));
+    g.ku = upd_kernel(tu.rows_radix, ip, maxM);
+    g.kg = gat_kernel(tu.rows_radix, ip, maxM);
+    g.kc = cols_kernel(tu.cols_radix, tu.cols_width, cip, maxM);
+    MRPIE_HIP(ensure_lds((const void*)g.ku, g.lu));
+    MRPIE_HIP(ensure_lds((const void*)g.kg, g.lu));
+    MRPIE_HIP(ensure_lds((const void*)g.kc, g.lc));
   } else {
     g.kr = rows_kernel(tu.rows_radix, ip, maxM);
     g.kc = cols_kernel(tu.cols_radix, tu.cols_width, cip, maxM);
@@ -853,6 +1082,14 @@ static void launch_tick(const PassGroup& g, const Common& c, int t) {
              jb.H, jb.W, jb.I, jb.status, c);
     if (t < g.maxTot)
       launch_k(TK_COLS, g.kc1, dim3(g.maxN / g.width, 1), blk, g.lc, g.s, jb.ws, jb.I, t, jb.J, jb.T, NM, jb.status);
+    return;
+  }
+  if (g.split) {
+    if (t > 0) launch_k(TK_UPD, g.ku, dim3(g.maxN, g.nb), g.rblk, g.lu, g.s, g.a, t);
+    if (t < g.maxTot) {
+      launch_k(TK_GAT, g.kg, dim3(g.maxN, g.nb), g.rblk, g.lu, g.s, g.a, t);
+      launch_k(TK_COLS, g.kc, dim3(g.maxN / g.width, g.nb), blk, g.lc, g.s, g.a, t);
+    }
     return;
   }
   launch_k(TK_ROWS, g.kr, dim3(g.maxN, g.nb), g.rblk, g.lr, g.s, g.a, t);
@@ -894,7 +1131,8 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
     for (const PassGroup& g : groups)
       if (g.maxTot > 0 && t <= g.maxTot) launch_tick(g, c, t);
   for (const PassGroup& g : groups) {
-    hipLaunchKernelGGL(k_probe_back, dim3(64, g.nb), dim3(256), 0, g.s, g.a);
+    // (the split passes update the probe in place: nothing to copy back)
+    if (!g.split) hipLaunchKernelGGL(k_probe_back, dim3(64, g.nb), dim3(256), 0, g.s, g.a);
     hipLaunchKernelGGL(k_finish, dim3(1, g.nb), dim3(256), 0, g.s, g.a, g.eo);
   }
   MRPIE_HIP(hipGetLastError());
@@ -1023,6 +1261,7 @@ int check_tuning(const mrpie_tuning* t) {
   if (t->lds_sweep < 0 || t->lds_sweep > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "lds_sweep must be in [0, 8]");
   if (t->cols_width != 1 && t->cols_width != 4) return fail(MRPIE_EINVAL, "cols_width must be 1 or 4");
   if (t->rows_inplace != 0 && t->rows_inplace != 1) return fail(MRPIE_EINVAL, "rows_inplace must be 0 or 1");
+  if (t->rows_split != 0 && t->rows_split != 1) return fail(MRPIE_EINVAL, "rows_split must be 0 or 1");
   return MRPIE_OK;
 }
 
@@ -1093,25 +1332,29 @@ int mrpie_rpie(const mrpie_problem* pb, const mrpie_params* pr, void* obj, void*
 
 int mrpie_set_tuning(int32_t N, int32_t M, int32_t batched, const mrpie_tuning* t) {
   if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
+  if (batched < 0 || batched > 2) return fail(MRPIE_EINVAL, "batched=%d not in {0, 1, 2}", batched);
   if (M < 0 || M > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "M=%d not in [0, 8]", M);
   int rc = check_tuning(t);
   if (rc) return rc;
-  set_tuning(N, M, batched ? 2 : 1,
-             Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width, t->rows_inplace});
+  set_tuning(N, M, batch_class_jobs(batched),
+             Tuning{t->rows_radix, t->cols_radix, t->rows_threads, t->lds_sweep, t->cols_width, t->rows_inplace,
+                    t->rows_split});
   return MRPIE_OK;
 }
 
 int mrpie_get_tuning(int32_t N, int32_t M, int32_t batched, mrpie_tuning* t) {
   if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
+  if (batched < 0 || batched > 2) return fail(MRPIE_EINVAL, "batched=%d not in {0, 1, 2}", batched);
   if (M < 1 || M > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "M=%d not in [1, 8]", M);
   if (!t) return fail(MRPIE_EINVAL, "tuning is NULL");
-  const Tuning u = get_tuning(N, M, batched ? 2 : 1);
+  const Tuning u = get_tuning(N, M, batch_class_jobs(batched));
   t->rows_radix = u.rows_radix;
   t->cols_radix = u.cols_radix;
   t->rows_threads = u.rows_threads;
   t->lds_sweep = u.lds_sweep;
   t->cols_width = u.cols_width;
   t->rows_inplace = u.rows_inplace;
+  t->rows_split = u.rows_split;
   return MRPIE_OK;
 }
 
@@ -1146,7 +1389,7 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
   Tuning tu{};
   if (tuning)
     tu = Tuning{tuning->rows_radix, tuning->cols_radix, tuning->rows_threads, tuning->lds_sweep, tuning->cols_width,
-                tuning->rows_inplace};
+                tuning->rows_inplace, tuning->rows_split};
   return run_sweep(c, recs.data(), njobs, errs.data(), (hipStream_t)stream, tuning ? &tu : nullptr);
 }
 

@@ -72,12 +72,16 @@ struct Tuning {
                      // one-workgroup sweep (0: never)
   int cols_width;    // 1 or 4 adjacent detector columns per column workgroup
   int rows_inplace;  // 1: multi-job row passes run their inverse FFTs in place
+  int rows_split;    // 1: multi-job calls run the update and the gather row
+                     // passes as launches of their own (three per position)
 };
 // The tuning of (N, mode class of M, batch class of nb jobs): the one set
 // for it, else the default.  set_tuning with M = 0 sets every mode class.
 Tuning get_tuning(int N, int M, int nb);
 void set_tuning(int N, int M, int nb, const Tuning& t);
 Tuning default_tuning(int N, int nb);
+// A job count of call class cls (0: one job, 1: 2-15 jobs, 2: 16 or more).
+int batch_class_jobs(int cls);
 // validates a caller's tuning (MRPIE_OK or MRPIE_EINVAL with a message)
 int check_tuning(const mrpie_tuning* t);
 

@@ -74,11 +74,13 @@ int candidates(int N, int M, bool batched, std::vector<Tuning>& out) {
     for (int cr : {4, 8})
       for (int th : {256, 512})
         for (int cw : {1, 4})
-          for (int ip : {0, 1}) {
-            if (ip && !batched) continue;  // the in-place option shapes multi-job launches only
-            out.push_back(Tuning{rr, cr, th, 0, cw, ip});
-          }
-  if (lds_sweep_fits(N, M)) out.push_back(Tuning{8, 8, 256, MRPIE_MAX_MODES, 1, 0});
+          for (int ip : {0, 1})
+            for (int sp : {0, 1}) {
+              // the in-place and split options shape multi-job launches only
+              if ((ip || sp) && !batched) continue;
+              out.push_back(Tuning{rr, cr, th, 0, cw, ip, sp});
+            }
+  if (lds_sweep_fits(N, M)) out.push_back(Tuning{8, 8, 256, MRPIE_MAX_MODES, 1, 0, 0});
   return (int)out.size();
 }
 
@@ -92,12 +94,13 @@ extern "C" {
 
 int mrpie_tuning_candidates(int32_t N, int32_t M, int32_t batched, mrpie_tuning* out, int32_t cap) {
   if (n_index(N) < 0) return fail(MRPIE_EUNSUPPORTED, "N=%d not in {32,64,128,192,256}", N);
+  if (batched < 0 || batched > 2) return fail(MRPIE_EINVAL, "batched=%d not in {0, 1, 2}", batched);
   if (M < 1 || M > MRPIE_MAX_MODES) return fail(MRPIE_EINVAL, "M=%d not in [1, 8]", M);
   std::vector<Tuning> c;
   const int n = candidates(N, M, batched != 0, c);
   for (int i = 0; out && i < std::min<int>(n, cap); ++i)
     out[i] = mrpie_tuning{c[i].rows_radix, c[i].cols_radix, c[i].rows_threads, c[i].lds_sweep, c[i].cols_width,
-                          c[i].rows_inplace};
+                          c[i].rows_inplace, c[i].rows_split};
   return n;
 }
 
@@ -136,7 +139,7 @@ int mrpie_autotune(int32_t N, int32_t M, int32_t batch, int32_t J, int32_t reps,
   std::vector<Tuning> cands;
   const bool batched = batch > 1;
   const int n = candidates(N, M, batched, cands);
-  const int nb = batched ? 2 : 1;
+  const int nb = batch;  // the call class of `batch` jobs
   const Tuning saved = get_tuning(N, M, nb);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   MRPIE_HIP(hipEventCreate(&e0));
@@ -174,7 +177,9 @@ int mrpie_autotune(int32_t N, int32_t M, int32_t batch, int32_t J, int32_t reps,
   }
   const Tuning& t = cands[best_i];
   set_tuning(N, M, nb, t);
-  if (best) *best = mrpie_tuning{t.rows_radix, t.cols_radix, t.rows_threads, t.lds_sweep, t.cols_width, t.rows_inplace};
+  if (best)
+    *best = mrpie_tuning{t.rows_radix, t.cols_radix, t.rows_threads, t.lds_sweep, t.cols_width, t.rows_inplace,
+                         t.rows_split};
   return MRPIE_OK;
 }
 

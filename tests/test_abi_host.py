@@ -128,16 +128,21 @@ def test_register_and_adam_argument_checks(lib):
 
 
 def _fields(t):
-    return (t.rows_radix, t.cols_radix, t.rows_threads, t.lds_sweep, t.cols_width, t.rows_inplace)
+    return (t.rows_radix, t.cols_radix, t.rows_threads, t.lds_sweep, t.cols_width, t.rows_inplace, t.rows_split)
 
 
 def test_tuning_round_trip(lib):
     d = _abi.Tuning()
     assert lib.mrpie_get_tuning(128, 3, 1, C.byref(d)) == 0
     assert (d.rows_radix, d.cols_radix, d.rows_threads, d.lds_sweep) == (8, 8, 256, 0)
-    assert (d.cols_width, d.rows_inplace) == (4, 1)  # batch class
+    assert (d.cols_width, d.rows_inplace, d.rows_split) == (4, 1, 0)  # batches of 2-15 jobs
+    dl = _abi.Tuning()
+    assert lib.mrpie_get_tuning(128, 3, 2, C.byref(dl)) == 0
+    assert (dl.cols_width, dl.rows_inplace, dl.rows_split) == (4, 1, 1)  # batches of 16 or more
+    assert lib.mrpie_get_tuning(128, 3, 3, C.byref(dl)) == _abi.MRPIE_EINVAL
     d0 = _abi.Tuning()
-    assert lib.mrpie_get_tuning(128, 3, 0, C.byref(d0)) == 0 and (d0.cols_width, d0.rows_inplace) == (1, 0)
+    assert lib.mrpie_get_tuning(128, 3, 0, C.byref(d0)) == 0
+    assert (d0.cols_width, d0.rows_inplace, d0.rows_split) == (1, 0, 0)
     d64 = _abi.Tuning()
     assert lib.mrpie_get_tuning(64, 1, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
     d32 = _abi.Tuning()
@@ -156,30 +161,37 @@ def test_tuning_round_trip(lib):
     assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 9, 1))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 2))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 3))) == _abi.MRPIE_EINVAL
+    assert lib.mrpie_set_tuning(128, 1, 1, C.byref(_abi.Tuning(8, 4, 256, 0, 1, 1, 2))) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(128, 9, 1, C.byref(t)) == _abi.MRPIE_EINVAL
     assert lib.mrpie_get_tuning(128, 0, 1, C.byref(u)) == _abi.MRPIE_EINVAL
     assert lib.mrpie_set_tuning(100, 1, 1, C.byref(t)) == _abi.MRPIE_EUNSUPPORTED
+    u2 = _abi.Tuning()
+    assert lib.mrpie_get_tuning(128, 3, 2, C.byref(u2)) == 0 and _fields(u2) == _fields(dl)  # other class
     assert lib.mrpie_set_tuning(128, 0, 1, C.byref(d)) == 0  # restore the default
     # N = 32 (the fifth probe size) has a table entry of its own
     t32 = _abi.Tuning(4, 4, 512, 2, 1, 0)
     assert lib.mrpie_set_tuning(32, 0, 0, C.byref(t32)) == 0
     u = _abi.Tuning()
     assert lib.mrpie_get_tuning(32, 2, 0, C.byref(u)) == 0 and _fields(u) == _fields(t32)
-    assert lib.mrpie_get_tuning(256, 2, 0, C.byref(u)) == 0 and _fields(u) == (8, 8, 256, 0, 1, 0)
+    assert lib.mrpie_get_tuning(256, 2, 0, C.byref(u)) == 0 and _fields(u) == (8, 8, 256, 0, 1, 0, 0)
     assert lib.mrpie_set_tuning(32, 0, 0, C.byref(d32)) == 0
 
 
 def test_autotuner_candidates_and_workspace(lib):
-    """The autotuner's candidate list (the in-place option only for batches,
-    the LDS sweep only where the modes fit it) and its workspace size; the
-    timing itself needs a GPU."""
+    """The autotuner's candidate list (the in-place and split options only
+    for batches, the LDS sweep only where the modes fit it) and its
+    workspace size; the timing itself needs a GPU."""
     assert lib.mrpie_tuning_candidates(256, 3, 0, None, 0) == 16
-    assert lib.mrpie_tuning_candidates(256, 3, 1, None, 0) == 32
+    assert lib.mrpie_tuning_candidates(256, 3, 1, None, 0) == 64
     assert lib.mrpie_tuning_candidates(64, 2, 0, None, 0) == 17
-    assert lib.mrpie_tuning_candidates(64, 5, 1, None, 0) == 32
+    assert lib.mrpie_tuning_candidates(64, 5, 1, None, 0) == 64
     arr = (_abi.Tuning * 17)()
     assert lib.mrpie_tuning_candidates(64, 2, 0, arr, 17) == 17
-    assert _fields(arr[16]) == (8, 8, 256, 8, 1, 0) and all(arr[i].rows_inplace == 0 for i in range(17))
+    assert _fields(arr[16]) == (8, 8, 256, 8, 1, 0, 0)
+    assert all(arr[i].rows_inplace == 0 and arr[i].rows_split == 0 for i in range(17))
+    arr = (_abi.Tuning * 64)()
+    assert lib.mrpie_tuning_candidates(256, 3, 1, arr, 64) == 64
+    assert {(arr[i].rows_inplace, arr[i].rows_split) for i in range(64)} == {(0, 0), (0, 1), (1, 0), (1, 1)}
     assert lib.mrpie_tuning_candidates(96, 2, 0, None, 0) == _abi.MRPIE_EUNSUPPORTED
     n = C.c_size_t(0)
     assert lib.mrpie_autotune_workspace_size(256, 3, 2, 16, C.byref(n)) == 0

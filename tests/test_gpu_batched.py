@@ -19,8 +19,10 @@ def _gpu():
     need_gpu()
 
 
-@pytest.mark.parametrize("inplace,width", [(0, 4), (1, 4), (0, 1)])
-def test_batched_equals_plain_per_job(inplace, width):
+@pytest.mark.parametrize("inplace,width,split", [(0, 4, 0), (1, 4, 0), (0, 1, 0), (0, 4, 1), (1, 4, 1), (0, 1, 1)])
+def test_batched_equals_plain_per_job(inplace, width, split):
+    """Fused row pass (split = 0) and split update / gather passes (split =
+    1), each FFT buffer option and column width."""
     from paper_2205_04295_amd import api, tune
     specs = [dict(seed=71, H=160, N=64, M=1, J=9), dict(seed=72, H=256, N=128, M=3, J=5),
              dict(seed=73, H=320, N=192, M=2, J=3), dict(seed=74, H=384, N=256, M=4, J=4),
@@ -34,7 +36,7 @@ def test_batched_equals_plain_per_job(inplace, width):
     # the launch's tuning is that of its largest probe size, batch class
     saved = tune.get_tuning(256, True)
     try:
-        tune.set_tuning(256, True, **dict(saved, rows_inplace=inplace, cols_width=width))
+        tune.set_tuning(256, True, **dict(saved, rows_inplace=inplace, cols_width=width, rows_split=split))
         api.rpie_batched(jobs, **prm)
         torch.cuda.synchronize()
     finally:

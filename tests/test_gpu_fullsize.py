@@ -88,14 +88,17 @@ def refine_w():
     return wl.refine_case(seed=2)
 
 
-@pytest.mark.parametrize("k,refine", [(1, 0), (1599, 0), (800, 1)])
-def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine):
+@pytest.mark.parametrize("k,refine,up", [(1, 0, 100), (1599, 0, 100), (800, 1, 100), (800, 1, 1000), (1234, 1, 1000)])
+def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine, up):
     """The subpixel (four-launch) step at full size, from the GPU's own state
     after k positions: box and probe after one more position match the
-    oracle; with refinement, the registered shift drives the same first Adam
-    step (the registration's peaks are exact)."""
+    oracle; with refinement, the measured shift (recovered from Adam's first
+    moment, m = (1 - b1) g at t = 1) agrees with the oracle's to the window
+    spacing and drives the same first Adam step.  At upsample 100 the shift
+    between a patch and its update rounds to 0 (no move on either side); at
+    1000 it does not."""
     w = refine_w
-    prm = dict(w.params, iterations=1, refine=refine, subpixel=1)
+    prm = dict(w.params, iterations=1, refine=refine, subpixel=1, upsample=up)
     J1 = 1
     ad = lambda n: np.zeros((n, 4), np.float32) if refine else None
     st = run_gpu(_prefix(w, k), prm, adam=ad(k))
@@ -119,8 +122,14 @@ def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine):
     assert np.array_equal(g["O"][outside], st["O"][outside])
     if refine:
         moved_g, moved_o = g["pos"][0] - w.pos0[k], ref["pos"][0] - w.pos0[k]
-        print(f"  Adam step gpu {moved_g} oracle {moved_o}")
-        assert np.max(np.abs(moved_g - moved_o)) < 1e-4
+        s_g = g["adam"][0, :2].astype(np.float64) / (1 - np.float32(prm["adam_b1"]))
+        s_o = ref["adam"][0, :2] / (1 - prm["adam_b1"])
+        print(f"  shift gpu {s_g} oracle {s_o}; Adam step gpu {moved_g} oracle {moved_o}")
+        assert np.max(np.abs(s_g - s_o)) <= 1.01 / up
+        if up == 1000:
+            assert np.any(s_o != 0)       # the case exercises a non-zero step
+        if np.max(np.abs(s_g - s_o)) < 0.5 / up:
+            assert np.max(np.abs(moved_g - moved_o)) < 1e-4
 
 
 @pytest.fixture(scope="module")

@@ -251,8 +251,8 @@ def test_every_launch_shape_matches_oracle(name):
     N = w.P0.shape[-1]
     saved = tune.get_tuning(N, False)
     try:
-        # rows_inplace only shapes multi-job launches
-        for cand in [c for c in tune.CANDIDATES if not c["rows_inplace"]]:
+        # rows_inplace and rows_split only shape multi-job launches
+        for cand in [c for c in tune.CANDIDATES if not c["rows_inplace"] and not c["rows_split"]]:
             tune.set_tuning(N, False, **cand)
             g = run_gpu(w, prm)
             assert rel_l2(g["O"], o["O"]) < 1e-4 and rel_l2(g["P"], o["P"]) < 1e-4, cand
@@ -267,7 +267,7 @@ def test_autotuner_installs_a_candidate():
     saved, saved256 = tune.get_tuning(64, False, M=2), tune.get_tuning(256, False, M=2)
     other = tune.get_tuning(64, False, M=8)
     try:
-        single = [c for c in tune.CANDIDATES if not c["rows_inplace"]]
+        single = [c for c in tune.CANDIDATES if not c["rows_inplace"] and not c["rows_split"]]
         best, times = tune.autotune(64, 2, batch=1, J=8, reps=1)
         cands = single + [tune.LDS_CANDIDATE]
         assert best in cands and len(times) == len(cands)
