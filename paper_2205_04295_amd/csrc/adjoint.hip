@@ -26,6 +26,9 @@
 
 namespace mrpie {
 
+// The FFT passes of this file run 256 threads per workgroup.
+constexpr int kAdjThreads = 256;
+
 __device__ __forceinline__ size_t chunk_off(int b, int N) { return (size_t)b * N * N; }
 
 // Single-field row passes take kAdjRows rows per workgroup, so that every
@@ -43,15 +46,15 @@ __device__ void adj_p1(const AdjArgs& a, float2* smem) {
   float2* B = A + kAdjRows * N;      // kAdjRows N
   const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
   const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
-  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) {
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
     const int rr = i / N, c = i - rr * N;
     A[i] = a.obj[(size_t)(ny + r0 + rr) * a.W + nx + c];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
-  float2* R = fft_lds<N, false, false>(A, B, kAdjRows, tw);
+  float2* R = fft_lds<N, false, false, kAdjThreads>(A, B, kAdjRows, tw);
   float2* cp = a.Cp + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) cp[i] = R[i];
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) cp[i] = R[i];
 }
 
 __device__ __forceinline__ void frac_of(const AdjArgs& a, int j, int N, float* fy, float* fx) {
@@ -101,7 +104,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
     if (q >= N * CW) continue;
     v[i] = cp[(size_t)k * N + u0 + c];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -109,7 +112,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
     A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, false>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false, kAdjThreads>(A, B, CW, tw);
   float2* G = (F == A) ? B : A;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -121,7 +124,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
     G[c * N + k] = cscale(fo, 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false>(G, F, CW, tw);
+  float2* H = fft_lds<N, true, false, kAdjThreads>(G, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -148,10 +151,10 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
     for (int p = 0; p < MM; ++p)
       if (p < M) P[p] = a.probe[p * NN + (size_t)r * N + c];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
   if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, true, false>(A, B, 1, tw);
+  float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, 1, tw);
   float2* W = (R == A) ? B : A;
   if (c < N) {
     const float2 o = R[c];
@@ -161,9 +164,9 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
       if (p < M) W[p * N + c] = cmul(P[p], o);
   }
   __syncthreads();
-  float2* S = fft_lds<N, false, false>(W, R, M, tw);
+  float2* S = fft_lds<N, false, false, kAdjThreads>(W, R, M, tw);
   float2* psi = a.Psi + (size_t)b * M * NN;
-  for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
+  for (int i = threadIdx.x; i < M * N; i += kAdjThreads) {
     const int p = i / N, cc = i - p * N;
     psi[p * NN + (size_t)r * N + cc] = S[i];
   }
@@ -194,14 +197,14 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
     for (int p = 0; p < MM; ++p)
       if (p < M) A[(p * CW + c) * N + k] = psi[p * NN + off];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
   float2* F;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, false, MM * CW, 256>(A, M * CW, tw);
+    fft_lds_inplace<N, false, false, MM * CW, 256, kAdjThreads>(A, M * CW, tw);
     F = A;
   } else {
-    F = fft_lds<N, false, false>(A, B, M * CW, tw);
+    F = fft_lds<N, false, false, kAdjThreads>(A, B, M * CW, tw);
   }
   float2* G = IP ? F : ((F == A) ? B : A);  // (in place: each thread rescales the pixels it reads)
   double e = 0.0;
@@ -230,10 +233,10 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
   __syncthreads();
   const float2* H;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, false, MM * CW, 256>(G, M * CW, tw);
+    fft_lds_inplace<N, true, false, MM * CW, 256, kAdjThreads>(G, M * CW, tw);
     H = G;
   } else {
-    H = fft_lds<N, true, false>(G, F, M * CW, tw);
+    H = fft_lds<N, true, false, kAdjThreads>(G, F, M * CW, tw);
   }
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -273,7 +276,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
     acc[p] = make_float2(0.f, 0.f);
     if (p < M && c < N) P[p] = a.probe[p * NN + roff];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
   for (int b = b0; b < b1; ++b) {
     float2* psi = a.Psi + (size_t)b * M * NN;
     float2 o = make_float2(0.f, 0.f);
@@ -284,7 +287,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
         if (p < M) A[p * N + c] = psi[p * NN + roff];
     }
     __syncthreads();
-    float2* R = fft_lds<N, true, false>(A, B, M, tw);
+    float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, M, tw);
     float2* W = (R == A) ? B : A;
     if (c < N) {
       float2 g = make_float2(0.f, 0.f);
@@ -298,7 +301,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
       W[c] = cscale(g, 2.f);
     }
     __syncthreads();
-    float2* S = fft_lds<N, false, false>(W, R, 1, tw);
+    float2* S = fft_lds<N, false, false, kAdjThreads>(W, R, 1, tw);
     if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
     __syncthreads();  // A, B are reused by the next position
   }
@@ -332,7 +335,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     if (q >= N * CW) continue;
     v[i] = g[(size_t)k * N + u0 + c];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kAdjThreads>(tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -340,7 +343,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     A[c * N + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, false>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false, kAdjThreads>(A, B, CW, tw);
   float2* G2 = (F == A) ? B : A;
   double gy = 0.0, gx = 0.0;
 #pragma unroll
@@ -358,7 +361,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     G2[c * N + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false>(G2, F, CW, tw);
+  float2* H = fft_lds<N, true, false, kAdjThreads>(G2, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -382,11 +385,11 @@ __device__ void adj_p7(const AdjArgs& a, float2* smem) {
   float2* A = tw + N;                // kAdjRows N
   float2* B = A + kAdjRows * N;      // kAdjRows N
   float2* g = a.G + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) A[i] = g[i];
-  load_twiddles<N>(tw);
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) A[i] = g[i];
+  load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
-  float2* R = fft_lds<N, true, false>(A, B, kAdjRows, tw);
-  for (int i = threadIdx.x; i < kAdjRows * N; i += blockDim.x) g[i] = R[i];
+  float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, kAdjRows, tw);
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) g[i] = R[i];
 }
 
 #define MRPIE_ADJ_KERNEL(NAME, FN)                       \
@@ -577,7 +580,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     a.nb = nb;
-    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(256);
+    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(kAdjThreads);
     hipLaunchKernelGGL(k_adj_p1, gr, blk, l1, s, a);
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);

@@ -60,16 +60,17 @@ static inline int launch_init_twiddles(hipStream_t s) {
   return MRPIE_OK;
 }
 
-// Copy the N-entry twiddle table to LDS.
-template <int N>
+// Copy the N-entry twiddle table to LDS (NT: the kernel's fixed workgroup
+// size, 0 = read blockDim.x).
+template <int N, int NT = 0>
 __device__ __forceinline__ void load_twiddles(float2* s_tw) {
   constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : N == 256 ? 3 : 4;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw[idx][i];
+  for (int i = threadIdx.x; i < N; i += wg_threads<NT>()) s_tw[i] = g_tw[idx][i];
 }
-template <int N>
+template <int N, int NT = 0>
 __device__ __forceinline__ void load_twiddles(double2* s_tw) {
   constexpr int idx = N == 64 ? 0 : N == 128 ? 1 : N == 192 ? 2 : N == 256 ? 3 : 4;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) s_tw[i] = g_tw64[idx][i];
+  for (int i = threadIdx.x; i < N; i += wg_threads<NT>()) s_tw[i] = g_tw64[idx][i];
 }
 
 // Wave reductions (64-wide waves, every lane active).  DPP row shifts by

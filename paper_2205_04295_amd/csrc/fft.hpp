@@ -130,15 +130,25 @@ template <> struct Plan4<128> { static constexpr int R[4] = {4, 4, 4, 2}; };
 template <> struct Plan4<192> { static constexpr int R[4] = {4, 4, 4, 3}; };
 template <> struct Plan4<256> { static constexpr int R[4] = {4, 4, 4, 4}; };
 
+// Threads per workgroup: NT when the caller's kernel has a fixed size,
+// else blockDim.x.  (blockDim.x is read from the implicit kernel arguments
+// with a vector load and a wait on every outstanding load, each time a
+// stage loop needs it; a compile-time size costs nothing.)
+template <int NT>
+__device__ __forceinline__ int wg_threads() {
+  if constexpr (NT > 0) return NT;
+  else return (int)blockDim.x;
+}
+
 // One Stockham stage over `nb` transforms of length N stored contiguously
 // (transform t at src + t*N).  tw: N-th roots w_N^e = exp(-2 pi i e / N).
-template <int N, int R, int NS, bool INV, typename C>
+template <int N, int R, int NS, bool INV, int NT = 0, typename C>
 __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__ dst, int nb,
                                       const C* __restrict__ tw) {
   constexpr int Q = N / R;
   constexpr int TWS = N / (NS * R);
   const int total = nb * Q;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+  for (int t = threadIdx.x; t < total; t += wg_threads<NT>()) {
     const int b = t / Q;
     const int j = t - b * Q;
     const C* s = src + b * N;
@@ -165,20 +175,21 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
 // Full N-point transforms of `nb` contiguous rows in LDS buffer `a`, using
 // `b` as the ping-pong partner.  Returns the buffer holding the result.
 // Callers must __syncthreads() before (data ready); the result is ready on
-// return (a barrier ends every stage).
-template <int N, bool INV, bool R4 = true, typename C>
+// return (a barrier ends every stage).  NT: the kernel's fixed workgroup
+// size (0: read blockDim.x).
+template <int N, bool INV, bool R4 = true, int NT = 0, typename C>
 __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
   using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
   constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-  stage<N, R0, 1, INV>(a, b, nb, tw);
+  stage<N, R0, 1, INV, NT>(a, b, nb, tw);
   __syncthreads();
-  stage<N, R1, R0, INV>(b, a, nb, tw);
+  stage<N, R1, R0, INV, NT>(b, a, nb, tw);
   __syncthreads();
   if constexpr (R2 == 1) return a;
-  stage<N, R2, R0 * R1, INV>(a, b, nb, tw);
+  stage<N, R2, R0 * R1, INV, NT>(a, b, nb, tw);
   __syncthreads();
   if constexpr (R3 == 1) return b;
-  stage<N, R3, R0 * R1 * R2, INV>(b, a, nb, tw);
+  stage<N, R3, R0 * R1 * R2, INV, NT>(b, a, nb, tw);
   __syncthreads();
   return a;
 }
@@ -188,7 +199,7 @@ __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
 // writes its outputs over the same buffer — one buffer instead of two, at
 // the price of a second barrier per stage.  MAXB bounds the butterflies per
 // thread (nb * N / R / blockDim.x, rounded up).
-template <int N, int R, int NS, bool INV, int MAXB, typename C>
+template <int N, int R, int NS, bool INV, int MAXB, int NT = 0, typename C>
 __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restrict__ tw) {
   constexpr int Q = N / R;
   constexpr int TWS = N / (NS * R);
@@ -197,7 +208,7 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
   int bs[MAXB], jj[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int t = threadIdx.x + i * blockDim.x;
+    const int t = threadIdx.x + i * wg_threads<NT>();
     bs[i] = 0;
     jj[i] = 0;
     if (t < total) {
@@ -211,7 +222,7 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int t = threadIdx.x + i * blockDim.x;
+    const int t = threadIdx.x + i * wg_threads<NT>();
     if (t < total) {
       const int j = jj[i];
       if constexpr (NS > 1) {
@@ -233,16 +244,17 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
 }
 
 // Full in-place transforms of `nb` (<= MAXNB) contiguous rows of `buf`
-// with at least `MINT` threads per workgroup.  Same contract as fft_lds;
-// the result is in `buf`.
-template <int N, bool INV, bool R4, int MAXNB, int MINT, typename C>
+// with at least `MINT` threads per workgroup (exactly NT when NT > 0).
+// Same contract as fft_lds; the result is in `buf`.
+template <int N, bool INV, bool R4, int MAXNB, int MINT, int NT = 0, typename C>
 __device__ void fft_lds_inplace(C* buf, int nb, const C* __restrict__ tw) {
   using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
   constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT>(buf, nb, tw);
-  stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT>(buf, nb, tw);
-  if constexpr (R2 > 1) stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT>(buf, nb, tw);
-  if constexpr (R3 > 1) stage_inplace<N, R3, R0 * R1 * R2, INV, (MAXNB * (N / R3) + MINT - 1) / MINT>(buf, nb, tw);
+  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT, NT>(buf, nb, tw);
+  stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT, NT>(buf, nb, tw);
+  if constexpr (R2 > 1) stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT, NT>(buf, nb, tw);
+  if constexpr (R3 > 1)
+    stage_inplace<N, R3, R0 * R1 * R2, INV, (MAXNB * (N / R3) + MINT - 1) / MINT, NT>(buf, nb, tw);
 }
 
 }  // namespace mrpie

@@ -477,7 +477,7 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
         if (p < M) v[i][p] = psi[p * NN + off];
     }
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, 256>(tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + NT * i;
@@ -491,10 +491,10 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   __syncthreads();
   float2* F;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, R4, MM * CW, 256>(bufA, M * CW, tw);
+    fft_lds_inplace<N, false, R4, MM * CW, 256, 256>(bufA, M * CW, tw);
     F = bufA;
   } else {
-    F = fft_lds<N, false, R4>(bufA, bufB, M * CW, tw);
+    F = fft_lds<N, false, R4, 256>(bufA, bufB, M * CW, tw);
   }
   float2* G = IP ? F : ((F == bufA) ? bufB : bufA);
   // Eq. 7: the 2-D transform here is unnormalised (N x unitary) and so is
@@ -529,10 +529,10 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   __syncthreads();
   float2* H;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, R4, MM * CW, 256>(G, M * CW, tw);
+    fft_lds_inplace<N, true, R4, MM * CW, 256, 256>(G, M * CW, tw);
     H = G;
   } else {
-    H = fft_lds<N, true, R4>(G, F, M * CW, tw);
+    H = fft_lds<N, true, R4, 256>(G, F, M * CW, tw);
   }
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -604,7 +604,7 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
 #pragma unroll
     for (int r = 0; r < RL; ++r) Iv[r] = Ij[(size_t)(tid + QL * r) * N + u];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, 256>(tw);
   // forward stage 1 (no twiddles) -> LDS
   if (s0) {
     dftR<R0, false>(v);
@@ -613,7 +613,7 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
   }
   __syncthreads();
   // forward stage 2, LDS -> LDS
-  stage<N, R1, R0, false>(bufA, bufB, M, tw);
+  stage<N, R1, R0, false, 256>(bufA, bufB, M, tw);
   __syncthreads();
   // forward stage 3 (every mode per thread), modulus, inverse stage 1
   double e = 0.0, isv = 0.0;
@@ -659,7 +659,7 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
   }
   __syncthreads();
   // inverse stage 2, LDS -> LDS
-  stage<N, R1, RL, true>(bufA, bufB, M, tw);
+  stage<N, R1, RL, true, 256>(bufA, bufB, M, tw);
   __syncthreads();
   // inverse stage 3 -> global
   if (s0) {

@@ -47,6 +47,10 @@
 
 namespace mrpie {
 
+// Every kernel of this file runs 256 threads per workgroup.
+constexpr int kSpThreads = 256;
+
+
 struct SpArgs {
   Common c;
   JobRec jb;
@@ -155,7 +159,7 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
       if (!(rb1 >= 0 && gx >= nx_p && gx < nx_p + N)) og = jb.obj[(size_t)(ny_n + r) * jb.W + gx];
     }
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kSpThreads>(tw);
   if (has_prev) {
     float2 e1 = d1, e2 = d2;
     if (fx_p != 0.f) {  // x back-move (db is already moved back along y)
@@ -164,7 +168,7 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
         A[N + c] = d2;
       }
       __syncthreads();
-      float2* F = fft_lds<N, false, false>(A, B, 2, tw);
+      float2* F = fft_lds<N, false, false, kSpThreads>(A, B, 2, tw);
       float2* G = (F == A) ? B : A;
       if (lane) {
         const float2 w = ramp1(c, fx_p, -1.f, N);
@@ -172,7 +176,7 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
         G[N + c] = cmul(F[N + c], w);
       }
       __syncthreads();
-      float2* H = fft_lds<N, true, false>(G, F, 2, tw);
+      float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 2, tw);
       if (lane) {
         e1 = H[c];
         e2 = H[N + c];
@@ -208,11 +212,11 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
   if (fx_n != 0.f) {
     if (lane) A[c] = v;
     __syncthreads();
-    float2* F = fft_lds<N, false, false>(A, B, 1, tw);
+    float2* F = fft_lds<N, false, false, kSpThreads>(A, B, 1, tw);
     float2* G = (F == A) ? B : A;
     if (lane) G[c] = cmul(F[c], ramp1(c, fx_n, 1.f, N));
     __syncthreads();
-    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 1, tw);
     if (lane) v = H[c];
   }
   if (lane) ((float2*)(ws + L.cb))[(size_t)r * N + c] = v;
@@ -247,16 +251,16 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
     for (int p = 0; p < MM; ++p)
       if (p < M) P[p] = Pc[p * NN + (size_t)k * N + u];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kSpThreads>(tw);
   float2 o = v;
   if (fy != 0.f) {  // y move
     if (lane) A[k] = v;
     __syncthreads();
-    float2* F = fft_lds<N, false, false>(A, B, 1, tw);
+    float2* F = fft_lds<N, false, false, kSpThreads>(A, B, 1, tw);
     float2* G = (F == A) ? B : A;
     if (lane) G[k] = cmul(F[k], ramp1(k, fy, 1.f, N));
     __syncthreads();
-    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 1, tw);
     if (lane) o = H[k];
     __syncthreads();
   }
@@ -277,7 +281,7 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
     ((float*)(ws + L.omax[0]))[u] = om;
     ((float*)(ws + L.pmax[0]))[u] = pm;
   }
-  float2* S = fft_lds<N, false, false>(A, B, M, tw);
+  float2* S = fft_lds<N, false, false, kSpThreads>(A, B, M, tw);
   if (a.fresnel > 0.f) {  // near field: y propagation, F_y^-1 h_y F_y
     float2* G = (S == A) ? B : A;
     if (lane) {
@@ -287,7 +291,7 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
         if (p < M) G[p * N + k] = cmul(S[p * N + k], h);
     }
     __syncthreads();
-    S = fft_lds<N, true, false>(G, S, M, tw);
+    S = fft_lds<N, true, false, kSpThreads>(G, S, M, tw);
   }
   float2* psi = (float2*)(ws + L.psi[0]);
   if (lane) {
@@ -327,10 +331,10 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
     for (int p = 0; p < MM; ++p)
       if (p < M) A[p * N + c] = psi[p * NN + (size_t)r * N + c];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kSpThreads>(tw);
   __syncthreads();
   const bool near = a.fresnel > 0.f;
-  float2* F = fft_lds<N, false, false>(A, B, M, tw);
+  float2* F = fft_lds<N, false, false, kSpThreads>(A, B, M, tw);
   float2* G = (F == A) ? B : A;
   if (near) {  // x propagation to the detector plane, F_x^-1 h_x F_x
     if (lane) {
@@ -340,7 +344,7 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
         if (p < M) G[p * N + c] = cmul(F[p * N + c], h);
     }
     __syncthreads();
-    F = fft_lds<N, true, false>(G, F, M, tw);
+    F = fft_lds<N, true, false, kSpThreads>(G, F, M, tw);
     G = (F == A) ? B : A;
   }
   // Eq. 7.  Far field: the 2-D transform here is unnormalised (N x unitary)
@@ -373,7 +377,7 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
   __syncthreads();
   float2* H;
   if (near) {  // back along x, F_x^-1 conj(h_x) F_x
-    float2* K = fft_lds<N, false, false>(G, F, M, tw);
+    float2* K = fft_lds<N, false, false, kSpThreads>(G, F, M, tw);
     float2* Q = (K == A) ? B : A;
     if (lane) {
       const float2 h = fresnel1(c, a.fresnel, 1.f, N);
@@ -382,9 +386,9 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
         if (p < M) Q[p * N + c] = cmul(K[p * N + c], h);
     }
     __syncthreads();
-    H = fft_lds<N, true, false>(Q, K, M, tw);
+    H = fft_lds<N, true, false, kSpThreads>(Q, K, M, tw);
   } else {
-    H = fft_lds<N, true, false>(G, F, M, tw);
+    H = fft_lds<N, true, false, kSpThreads>(G, F, M, tw);
   }
   if (lane) {
 #pragma unroll
@@ -437,12 +441,12 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
     om_in = ((const float*)(ws + L.omax[0]))[k];
     pm_in = ((const float*)(ws + L.pmax[0]))[k];
   }
-  load_twiddles<N>(tw);
+  load_twiddles<N, kSpThreads>(tw);
   float omax, pmaxv;
   block_max2(om_in, pm_in, redf, omax, pmaxv);  // (its barriers also publish A)
   float2* R;
   if (a.fresnel > 0.f) {  // near field: back along y, F_y^-1 conj(h_y) F_y
-    float2* F = fft_lds<N, false, false>(A, B, M, tw);
+    float2* F = fft_lds<N, false, false, kSpThreads>(A, B, M, tw);
     float2* G = (F == A) ? B : A;
     if (lane) {
       const float2 h = fresnel1(k, a.fresnel, 1.f, N);
@@ -451,9 +455,9 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
         if (p < M) G[p * N + k] = cmul(F[p * N + k], h);
     }
     __syncthreads();
-    R = fft_lds<N, true, false>(G, F, M, tw);
+    R = fft_lds<N, true, false, kSpThreads>(G, F, M, tw);
   } else {
-    R = fft_lds<N, true, false>(A, B, M, tw);
+    R = fft_lds<N, true, false, kSpThreads>(A, B, M, tw);
   }
   float2* W = (R == A) ? B : A;
   const int it_abs = cm.iter_offset + t / jb.J;
@@ -485,11 +489,11 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
   if (fy != 0.f) {  // y back-move of delta_o
     if (lane) W[k] = dlt;
     __syncthreads();
-    float2* F = fft_lds<N, false, false>(W, R, 1, tw);
+    float2* F = fft_lds<N, false, false, kSpThreads>(W, R, 1, tw);
     float2* G = (F == W) ? R : W;
     if (lane) G[k] = cmul(F[k], ramp1(k, fy, -1.f, N));
     __syncthreads();
-    float2* H = fft_lds<N, true, false>(G, F, 1, tw);
+    float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 1, tw);
     if (lane) dlt = H[k];
   }
   if (lane) ((float2*)(ws + L.db))[(size_t)k * N + u] = dlt;
@@ -555,7 +559,7 @@ int run_sweep_subpixel(const Common& c, const JobRec& jb, const SubpixelExtra& e
   MRPIE_HIP(ensure_lds((const void*)k_sp_cols_exit, lm));
   MRPIE_HIP(ensure_lds((const void*)k_sp_rows_mod, lm));
   MRPIE_HIP(ensure_lds((const void*)k_sp_cols_update, lm));
-  const dim3 g(N), blk(256);
+  const dim3 g(N), blk(kSpThreads);
 #define MRPIE_SP_LAUNCH(K, L, T_, MODE)                                                                        \
   hipLaunchKernelGGL(K, g, blk, L, s, jb.pos, jb.ws, jb.obj, jb.probe, T_, MODE, jb.J, jb.T, NM, jb.H, jb.W, jb.I, \
                      jb.status, ex.reg_ref, ex.reg_mov, ex.subpixel, ex.record_start, ex.xcb, ex.fresnel, c)
