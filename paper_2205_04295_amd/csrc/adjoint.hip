@@ -42,19 +42,23 @@ __device__ void adj_p1(const AdjArgs& a, float2* smem) {
   const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
   const int j = a.j0 + b;
   float2* tw = smem;
-  float2* A = tw + N;                // kAdjRows N
-  float2* B = A + kAdjRows * N;      // kAdjRows N
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
+  float2* A = tw + N;                // kAdjRows PT
+  float2* B = A + kAdjRows * PT;     // kAdjRows PT
   const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
   const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
   for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
     const int rr = i / N, c = i - rr * N;
-    A[i] = a.obj[(size_t)(ny + r0 + rr) * a.W + nx + c];
+    A[rr * PT + c] = a.obj[(size_t)(ny + r0 + rr) * a.W + nx + c];
   }
   load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
-  float2* R = fft_lds<N, false, false, kAdjThreads>(A, B, kAdjRows, tw);
+  float2* R = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, kAdjRows, tw);
   float2* cp = a.Cp + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) cp[i] = R[i];
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
+    const int rr = i / N, c = i - rr * N;
+    cp[i] = R[rr * PT + c];
+  }
 }
 
 __device__ __forceinline__ void frac_of(const AdjArgs& a, int j, int N, float* fy, float* fx) {
@@ -88,6 +92,7 @@ __device__ __forceinline__ int col_group(int nunits) {
 template <int N>
 __device__ void adj_p2(const AdjArgs& a, float2* smem) {
   constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
+  constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   const int u = col_group(gridDim.x), b = blockIdx.y;
   if (u >= N / CW) return;
   const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
@@ -95,7 +100,7 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
   frac_of(a, j, N, &fy, &fx);
   float2* tw = smem;
   float2* A = tw + N;       // transform c at c * N
-  float2* B = A + CW * N;
+  float2* B = A + CW * PT;
   float2* cp = a.Cp + chunk_off(b, N);
   float2 v[PIX];
 #pragma unroll
@@ -109,27 +114,27 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    A[c * N + k] = v[i];
+    A[c * PT + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, false, kAdjThreads>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, CW, tw);
   float2* G = (F == A) ? B : A;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
     if (q >= N * CW) continue;
     const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
-    const float2 fo = cmul(F[c * N + k], ramp(ky, kx, fy, fx, 1.f, N));
+    const float2 fo = cmul(F[c * PT + k], ramp(ky, kx, fy, fx, 1.f, N));
     a.Fo[chunk_off(b, N) + (size_t)k * N + uc] = fo;
-    G[c * N + k] = cscale(fo, 1.f / ((float)N * (float)N));
+    G[c * PT + k] = cscale(fo, 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false, kAdjThreads>(G, F, CW, tw);
+  float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(G, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    cp[(size_t)k * N + u0 + c] = H[c * N + k];
+    cp[(size_t)k * N + u0 + c] = H[c * PT + k];
   }
 }
 
@@ -140,8 +145,9 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
   const int r = blockIdx.x, b = blockIdx.y, M = a.M;
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
-  float2* A = tw + N;            // (M+1) N
-  float2* B = A + (M + 1) * N;   // (M+1) N
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
+  float2* A = tw + N;            // (M+1) PT
+  float2* B = A + (M + 1) * PT;  // (M+1) PT
   const int c = threadIdx.x;
   float2* cp = a.Cp + chunk_off(b, N);
   float2 v = make_float2(0.f, 0.f), P[MM];
@@ -154,21 +160,21 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
   load_twiddles<N, kAdjThreads>(tw);
   if (c < N) A[c] = v;
   __syncthreads();
-  float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, 1, tw);
+  float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, 1, tw);
   float2* W = (R == A) ? B : A;
   if (c < N) {
     const float2 o = R[c];
     cp[(size_t)r * N + c] = o;  // Cp now holds o
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) W[p * N + c] = cmul(P[p], o);
+      if (p < M) W[p * PT + c] = cmul(P[p], o);
   }
   __syncthreads();
-  float2* S = fft_lds<N, false, false, kAdjThreads>(W, R, M, tw);
+  float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, M, tw);
   float2* psi = a.Psi + (size_t)b * M * NN;
   for (int i = threadIdx.x; i < M * N; i += kAdjThreads) {
     const int p = i / N, cc = i - p * N;
-    psi[p * NN + (size_t)r * N + cc] = S[i];
+    psi[p * NN + (size_t)r * N + cc] = S[p * PT + cc];
   }
 }
 
@@ -183,8 +189,9 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
   const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
-  float2* A = tw + N;          // transform (p, c) at (p * CW + c) * N
-  float2* B = IP ? A : A + M * CW * N;
+  constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
+  float2* A = tw + N;          // transform (p, c) at (p * CW + c) * PT
+  float2* B = IP ? A : A + M * CW * PT;
   __shared__ double redd[16];
   float2* psi = a.Psi + (size_t)b * M * NN;
   const float* Ij = a.I + (size_t)j * NN;
@@ -195,16 +202,16 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
     const size_t off = (size_t)k * N + u0 + c;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) A[(p * CW + c) * N + k] = psi[p * NN + off];
+      if (p < M) A[(p * CW + c) * PT + k] = psi[p * NN + off];
   }
   load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
   float2* F;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, false, MM * CW, 256, kAdjThreads>(A, M * CW, tw);
+    fft_lds_inplace<N, false, false, MM * CW, 256, kAdjThreads, PT, true>(A, M * CW, tw);
     F = A;
   } else {
-    F = fft_lds<N, false, false, kAdjThreads>(A, B, M * CW, tw);
+    F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, M * CW, tw);
   }
   float2* G = IP ? F : ((F == A) ? B : A);  // (in place: each thread rescales the pixels it reads)
   double e = 0.0;
@@ -216,7 +223,7 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
     float S = 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) S += cabs2(F[(p * CW + c) * N + k]);
+      if (p < M) S += cabs2(F[(p * CW + c) * PT + k]);
     // hardware reciprocal square root and square root (about 1 ulp)
     const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
     const float Au = S * rs;
@@ -228,15 +235,15 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
     const float wgt = S > 0.f ? (1.f - sq * (float)N * rs) * invN * invN : 0.f;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) G[(p * CW + c) * N + k] = cscale(F[(p * CW + c) * N + k], wgt);
+      if (p < M) G[(p * CW + c) * PT + k] = cscale(F[(p * CW + c) * PT + k], wgt);
   }
   __syncthreads();
   const float2* H;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, false, MM * CW, 256, kAdjThreads>(G, M * CW, tw);
+    fft_lds_inplace<N, true, false, MM * CW, 256, kAdjThreads, PT, true>(G, M * CW, tw);
     H = G;
   } else {
-    H = fft_lds<N, true, false, kAdjThreads>(G, F, M * CW, tw);
+    H = fft_lds<N, true, false, kAdjThreads, PT, true>(G, F, M * CW, tw);
   }
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -245,7 +252,7 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
     const size_t off = (size_t)k * N + u0 + c;
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + off] = H[(p * CW + c) * N + k];
+      if (p < M) psi[p * NN + off] = H[(p * CW + c) * PT + k];
   }
   e = block_sum(e, redd);
   // one partial per column group, in the slot of its first column
@@ -266,8 +273,9 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
   const int b0 = blockIdx.y * kAdjGroup, b1 = min(b0 + kAdjGroup, a.nb);
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
-  float2* A = tw + N;       // M N
-  float2* B = A + M * N;    // M N
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
+  float2* A = tw + N;       // M PT
+  float2* B = A + M * PT;   // M PT
   const int c = threadIdx.x;
   const size_t roff = (size_t)r * N + c;
   float2 P[MM], acc[MM];
@@ -284,24 +292,24 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
       o = a.Cp[chunk_off(b, N) + roff];
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) A[p * N + c] = psi[p * NN + roff];
+        if (p < M) A[p * PT + c] = psi[p * NN + roff];
     }
     __syncthreads();
-    float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, M, tw);
+    float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, M, tw);
     float2* W = (R == A) ? B : A;
     if (c < N) {
       float2 g = make_float2(0.f, 0.f);
 #pragma unroll
       for (int p = 0; p < MM; ++p)
         if (p < M) {
-          const float2 chi = R[p * N + c];
+          const float2 chi = R[p * PT + c];
           acc[p] = cadd(acc[p], cscale(cmulc(chi, o), 2.f));   // 2 chi conj(o)
           g = cadd(g, cmulc(chi, P[p]));
         }
       W[c] = cscale(g, 2.f);
     }
     __syncthreads();
-    float2* S = fft_lds<N, false, false, kAdjThreads>(W, R, 1, tw);
+    float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, 1, tw);
     if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
     __syncthreads();  // A, B are reused by the next position
   }
@@ -317,6 +325,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
 template <int N>
 __device__ void adj_p6(const AdjArgs& a, float2* smem) {
   constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
+  constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   const int u = col_group(gridDim.x), b = blockIdx.y;
   if (u >= N / CW) return;
   const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
@@ -324,7 +333,7 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
   frac_of(a, j, N, &fy, &fx);
   float2* tw = smem;
   float2* A = tw + N;
-  float2* B = A + CW * N;
+  float2* B = A + CW * PT;
   __shared__ double redd[16];
   float2* g = a.G + chunk_off(b, N);
   const float2* Fo = a.Fo + chunk_off(b, N);
@@ -340,10 +349,10 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    A[c * N + k] = v[i];
+    A[c * PT + k] = v[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, false, kAdjThreads>(A, B, CW, tw);
+  float2* F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, CW, tw);
   float2* G2 = (F == A) ? B : A;
   double gy = 0.0, gx = 0.0;
 #pragma unroll
@@ -351,22 +360,22 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
     if (q >= N * CW) continue;
     const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
-    const float2 fg = F[c * N + k];
+    const float2 fg = F[c * PT + k];
     // Re conj(Fg) (i w) Fo = -w Im(conj(Fg) Fo), w = 2 pi k / N; unitary
     // spectra are the unnormalised ones / N
     const float2 cf = cmulc(Fo[(size_t)k * N + uc], fg);  // Fo conj(Fg)
     const double im = (double)cf.y / ((double)N * (double)N);
     gy += -2.0 * M_PI * (double)ky / (double)N * im;
     gx += -2.0 * M_PI * (double)kx / (double)N * im;
-    G2[c * N + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
+    G2[c * PT + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false, kAdjThreads>(G2, F, CW, tw);
+  float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(G2, F, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    g[(size_t)k * N + u0 + c] = H[c * N + k];
+    g[(size_t)k * N + u0 + c] = H[c * PT + k];
   }
   gy = block_sum(gy, redd);
   gx = block_sum(gx, redd);
@@ -382,14 +391,21 @@ template <int N>
 __device__ void adj_p7(const AdjArgs& a, float2* smem) {
   const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
   float2* tw = smem;
-  float2* A = tw + N;                // kAdjRows N
-  float2* B = A + kAdjRows * N;      // kAdjRows N
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
+  float2* A = tw + N;                // kAdjRows PT
+  float2* B = A + kAdjRows * PT;     // kAdjRows PT
   float2* g = a.G + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) A[i] = g[i];
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
+    const int rr = i / N, c = i - rr * N;
+    A[rr * PT + c] = g[i];
+  }
   load_twiddles<N, kAdjThreads>(tw);
   __syncthreads();
-  float2* R = fft_lds<N, true, false, kAdjThreads>(A, B, kAdjRows, tw);
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) g[i] = R[i];
+  float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, kAdjRows, tw);
+  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
+    const int rr = i / N, c = i - rr * N;
+    g[i] = R[rr * PT + c];
+  }
 }
 
 #define MRPIE_ADJ_KERNEL(NAME, FN)                       \
@@ -568,8 +584,12 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   }
   // LDS of the row passes (one / M+1 / M transforms), of the single-field
   // column passes (kAdjCW1 transforms) and of the mode column pass
-  const size_t l1 = (size_t)(N + 2 * kAdjRows * N) * 8, lm1 = (size_t)(N + 2 * (M + 1) * N) * 8, lm = (size_t)(N + 2 * M * N) * 8;
-  const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * N) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * N) * 8;
+  // row passes: transforms at the padded pitch col_pitch<N, 1, true>()
+  const size_t pr = (size_t)(N + N / 16 + 15) / 16 * 16;
+  const size_t l1 = (N + 2 * kAdjRows * pr) * 8, lm1 = (N + 2 * (M + 1) * pr) * 8, lm = (N + 2 * M * pr) * 8;
+  // (column passes: transforms at the pitch col_pitch<N, CW, true>())
+  const size_t pbase = (size_t)(N + N / 16 + 15) / 16 * 16, p1 = pbase + 16 / kAdjCW1, pm = pbase + 16 / kAdjCWM;
+  const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * p1) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * pm) * 8;
   MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p2, lc1));

@@ -142,20 +142,38 @@ __device__ __forceinline__ int wg_threads() {
 
 // One Stockham stage over `nb` transforms of length N stored contiguously
 // (transform t at src + t*N).  tw: N-th roots w_N^e = exp(-2 pi i e / N).
-template <int N, int R, int NS, bool INV, int NT = 0, typename C>
+// Padded layout of the buffers between two stages (opt-in): element i of a
+// transform sits at i + i / 16.  The first stage of a Stockham plan writes
+// each thread's R outputs to R consecutive elements, so in the natural
+// layout the 16 lanes an LDS access serves at once write 8R bytes apart and
+// share a handful of banks (8-way for radix 8); one pad element every 16
+// spreads them over distinct banks.  Inputs of the first stage and outputs
+// of the last stay in the natural layout, so callers never see the padding.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int padded_len() {
+  return N + N / 16;
+}
+
+// PITCH: distance in elements between consecutive transforms (>= N, or >=
+// padded_len<N>() with padded intermediates); PIN / POUT: the stage reads /
+// writes the padded layout.
+template <int N, int R, int NS, bool INV, int NT = 0, int PITCH = N, bool PIN = false, bool POUT = false,
+          typename C>
 __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__ dst, int nb,
                                       const C* __restrict__ tw) {
+  static_assert(!(PIN || POUT) || PITCH >= padded_len<N>(), "padded layout needs a longer pitch");
   constexpr int Q = N / R;
   constexpr int TWS = N / (NS * R);
   const int total = nb * Q;
   for (int t = threadIdx.x; t < total; t += wg_threads<NT>()) {
     const int b = t / Q;
     const int j = t - b * Q;
-    const C* s = src + b * N;
-    C* d = dst + b * N;
+    const C* s = src + b * PITCH;
+    C* d = dst + b * PITCH;
     C v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = s[j + r * Q];
+    for (int r = 0; r < R; ++r) v[r] = s[PIN ? pad16(j + r * Q) : j + r * Q];
     if constexpr (NS > 1) {
       const int k = j % NS;
 #pragma unroll
@@ -168,7 +186,7 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
     dftR<R, INV>(v);
     const int o = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) d[o + r * NS] = v[r];
+    for (int r = 0; r < R; ++r) d[POUT ? pad16(o + r * NS) : o + r * NS] = v[r];
   }
 }
 
@@ -176,20 +194,21 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
 // `b` as the ping-pong partner.  Returns the buffer holding the result.
 // Callers must __syncthreads() before (data ready); the result is ready on
 // return (a barrier ends every stage).  NT: the kernel's fixed workgroup
-// size (0: read blockDim.x).
-template <int N, bool INV, bool R4 = true, int NT = 0, typename C>
+// size (0: read blockDim.x); PITCH: transform b starts at element b * PITCH;
+// PAD: padded layout between stages (PITCH >= padded_len<N>()).
+template <int N, bool INV, bool R4 = true, int NT = 0, int PITCH = N, bool PAD = false, typename C>
 __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
   using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
   constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-  stage<N, R0, 1, INV, NT>(a, b, nb, tw);
+  stage<N, R0, 1, INV, NT, PITCH, false, PAD>(a, b, nb, tw);
   __syncthreads();
-  stage<N, R1, R0, INV, NT>(b, a, nb, tw);
+  stage<N, R1, R0, INV, NT, PITCH, PAD, PAD && (R2 > 1)>(b, a, nb, tw);
   __syncthreads();
   if constexpr (R2 == 1) return a;
-  stage<N, R2, R0 * R1, INV, NT>(a, b, nb, tw);
+  stage<N, R2, R0 * R1, INV, NT, PITCH, PAD, PAD && (R3 > 1)>(a, b, nb, tw);
   __syncthreads();
   if constexpr (R3 == 1) return b;
-  stage<N, R3, R0 * R1 * R2, INV, NT>(b, a, nb, tw);
+  stage<N, R3, R0 * R1 * R2, INV, NT, PITCH, PAD, false>(b, a, nb, tw);
   __syncthreads();
   return a;
 }
@@ -199,8 +218,10 @@ __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
 // writes its outputs over the same buffer — one buffer instead of two, at
 // the price of a second barrier per stage.  MAXB bounds the butterflies per
 // thread (nb * N / R / blockDim.x, rounded up).
-template <int N, int R, int NS, bool INV, int MAXB, int NT = 0, typename C>
+template <int N, int R, int NS, bool INV, int MAXB, int NT = 0, int PITCH = N, bool PIN = false, bool POUT = false,
+          typename C>
 __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restrict__ tw) {
+  static_assert(!(PIN || POUT) || PITCH >= padded_len<N>(), "padded layout needs a longer pitch");
   constexpr int Q = N / R;
   constexpr int TWS = N / (NS * R);
   const int total = nb * Q;
@@ -213,10 +234,10 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
     jj[i] = 0;
     if (t < total) {
       const int b = t / Q, j = t - b * Q;
-      bs[i] = b * N;
+      bs[i] = b * PITCH;
       jj[i] = j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[b * N + j + r * Q];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[b * PITCH + (PIN ? pad16(j + r * Q) : j + r * Q)];
     }
   }
   __syncthreads();
@@ -237,7 +258,7 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
       dftR<R, INV>(v[i]);
       const int o = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[bs[i] + o + r * NS] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[bs[i] + (POUT ? pad16(o + r * NS) : o + r * NS)] = v[i][r];
     }
   }
   __syncthreads();
@@ -246,15 +267,31 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
 // Full in-place transforms of `nb` (<= MAXNB) contiguous rows of `buf`
 // with at least `MINT` threads per workgroup (exactly NT when NT > 0).
 // Same contract as fft_lds; the result is in `buf`.
-template <int N, bool INV, bool R4, int MAXNB, int MINT, int NT = 0, typename C>
+template <int N, bool INV, bool R4, int MAXNB, int MINT, int NT = 0, int PITCH = N, bool PAD = false, typename C>
 __device__ void fft_lds_inplace(C* buf, int nb, const C* __restrict__ tw) {
   using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
   constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT, NT>(buf, nb, tw);
-  stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT, NT>(buf, nb, tw);
-  if constexpr (R2 > 1) stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT, NT>(buf, nb, tw);
+  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT, NT, PITCH, false, PAD>(buf, nb, tw);
+  stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT, NT, PITCH, PAD, PAD && (R2 > 1)>(buf, nb, tw);
+  if constexpr (R2 > 1)
+    stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT, NT, PITCH, PAD, PAD && (R3 > 1)>(
+        buf, nb, tw);
   if constexpr (R3 > 1)
-    stage_inplace<N, R3, R0 * R1 * R2, INV, (MAXNB * (N / R3) + MINT - 1) / MINT, NT>(buf, nb, tw);
+    stage_inplace<N, R3, R0 * R1 * R2, INV, (MAXNB * (N / R3) + MINT - 1) / MINT, NT, PITCH, PAD, false>(buf, nb, tw);
+}
+
+// LDS pitch (complex float elements) of the transforms of a column pass that
+// holds CW adjacent detector columns: its global-to-LDS transposes put
+// consecutive lanes on consecutive columns, so with a pitch of N (a multiple
+// of 32 elements) the CW lanes of one row hit the same LDS banks; 16 / CW
+// extra elements move each column's transform to other banks, so the 16 lanes
+// an LDS access serves at once touch 16 distinct bank pairs.
+// With padded intermediates (PAD) the pitch starts from padded_len<N>()
+// rounded up to 16 elements.
+template <int N, int CW, bool PAD = false>
+constexpr int col_pitch() {
+  constexpr int base = PAD ? (padded_len<N>() + 15) / 16 * 16 : N;
+  return CW > 1 ? base + 16 / CW : base;
 }
 
 }  // namespace mrpie

@@ -44,7 +44,9 @@ __device__ __forceinline__ size_t pick(const size_t (&a)[2], int i) { return i ?
 
 // IP: the inverse row FFTs run in place (one 3MN buffer instead of two:
 // more workgroups per CU, one more barrier per stage) — for batches.
-template <int N, bool R4, int MM, bool IP = false>
+// PAD: padded layout between FFT stages (fewer LDS bank conflicts: pays in
+// batches; a single job's latency chain only sees its extra index arithmetic)
+template <int N, bool R4, int MM, bool IP = false, bool PAD = true>
 __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
   const int M = jb.M;
   const int total = jb.J * jb.T;
@@ -59,10 +61,11 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   const int tid = threadIdx.x;
   const bool lane = tid < N;  // this thread owns column `tid`
 
+  constexpr int PT = col_pitch<N, 1, PAD>();  // LDS pitch of a transform
   float2* tw = smem;               // N
   float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
-  float2* bufA = orow + N;         // 2*M*N
-  float2* bufB = IP ? bufA + M * N : bufA + 2 * M * N;  // forward-FFT partner (IP: inside bufA)
+  float2* bufA = orow + N;         // 2*M*PT
+  float2* bufB = IP ? bufA + M * PT : bufA + 2 * M * PT;  // forward-FFT partner (IP: inside bufA)
   __shared__ float redf[32];
 
   const float2* psi_prev = (const float2*)(ws + pick(L.psi, prv));
@@ -165,17 +168,17 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
         if (q >= ns) break;
 #pragma unroll
         for (int p = 0; p < MM; ++p)
-          if (p < M) bufA[(q * M + p) * N + c] = pv[q][p];
+          if (p < M) bufA[(q * M + p) * PT + c] = pv[q][p];
       }
     }
     float omax, pmaxv;
     block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
     float2* res;
     if constexpr (IP) {
-      fft_lds_inplace<N, true, R4, 2 * MM, 256>(bufA, ns * M, tw);
+      fft_lds_inplace<N, true, R4, 2 * MM, 256, 0, PT, PAD>(bufA, ns * M, tw);
       res = bufA;
     } else {
-      res = fft_lds<N, true, R4>(bufA, bufB, ns * M, tw);
+      res = fft_lds<N, true, R4, 0, PT, PAD>(bufA, bufB, ns * M, tw);
     }
 
     // ---- probe update of row r (Eq. 5) from the pre-update o and P
@@ -191,7 +194,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
       for (int p = 0; p < MM; ++p)
         if (p < M) {
           const float2 P = Pq[0][p];
-          const float2 d = csub(res[p * N + c], cmul(P, o));
+          const float2 d = csub(res[p * PT + c], cmul(P, o));
           Pn[p] = cadd(P, cscale(cmulc(d, o), g));
           Pnew[p * NN + (size_t)r * N + c] = Pn[p];
           ps += cabs2(Pn[p]);
@@ -214,7 +217,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
         for (int p = 0; p < MM; ++p)
           if (p < M) {
             const float2 P = Pq[q][p];
-            const float2 d = csub(res[(q * M + p) * N + c], cmul(P, o));
+            const float2 d = csub(res[(q * M + p) * PT + c], cmul(P, o));
             num = cadd(num, cmulc(d, P));
             Ps += cabs2(P);
           }
@@ -249,7 +252,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     for (int p = 0; p < MM; ++p)
       if (p < M) {
         ps += cabs2(Pn[p]);
-        bufA[p * N + c] = cmul(Pn[p], o);
+        bufA[p * PT + c] = cmul(Pn[p], o);
       }
     pm_row = ps;
   }
@@ -259,11 +262,11 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     ((float*)(ws + pick(L.omax, cur)))[r] = om;
     ((float*)(ws + pick(L.pmax, cur)))[r] = pm;
   }
-  float2* res = fft_lds<N, false, R4>(bufA, bufB, M, tw);
+  float2* res = fft_lds<N, false, R4, 0, PT, PAD>(bufA, bufB, M, tw);
   float2* dst = (float2*)(ws + pick(L.psi, cur));
   for (int i = tid; i < M * N; i += blockDim.x) {
     const int p = i / N, cc = i - p * N;
-    dst[p * NN + (size_t)r * N + cc] = res[i];
+    dst[p * NN + (size_t)r * N + cc] = res[p * PT + cc];
   }
   if (i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
@@ -296,9 +299,10 @@ __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int
   const size_t NN = (size_t)N * N;
   const int tid = threadIdx.x, c = tid;
   const bool lane = tid < N;
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch of a transform (padded intermediates)
   float2* tw = smem;
   float2* bufA = tw + N;
-  float2* bufB = bufA + M * N;  // ping-pong partner (not used in place)
+  float2* bufB = bufA + M * PT;  // ping-pong partner (not used in place)
   __shared__ float redf[32];
 
   const float2* psi = (const float2*)(jb.ws + pick(L.psi, prv));
@@ -325,16 +329,16 @@ __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int
   if (lane) {
 #pragma unroll
     for (int p = 0; p < MM; ++p)
-      if (p < M) bufA[p * N + c] = pv[p];
+      if (p < M) bufA[p * PT + c] = pv[p];
   }
   float omax, pmaxv;
   block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
   float2* res;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, R4, MM, 256>(bufA, M, tw);
+    fft_lds_inplace<N, true, R4, MM, 256, 0, PT, true>(bufA, M, tw);
     res = bufA;
   } else {
-    res = fft_lds<N, true, R4>(bufA, bufB, M, tw);
+    res = fft_lds<N, true, R4, 0, PT, true>(bufA, bufB, M, tw);
   }
   const int it_abs = cm.iter_offset + st / jb.J;
   const bool upd_p = it_abs >= cm.probe_update_start;
@@ -349,7 +353,7 @@ __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int
     for (int p = 0; p < MM; ++p)
       if (p < M) {
         const float2 P = Pq[p];
-        const float2 d = csub(res[p * N + c], cmul(P, o));
+        const float2 d = csub(res[p * PT + c], cmul(P, o));
         const float2 Pn = cadd(P, cscale(cmulc(d, o), gP));
         prow[p * NN + c] = Pn;
         ps += cabs2(Pn);
@@ -380,9 +384,10 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
   const size_t NN = (size_t)N * N;
   const int tid = threadIdx.x, c = tid;
   const bool lane = tid < N;
+  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch of a transform (padded intermediates)
   float2* tw = smem;
   float2* bufA = tw + N;
-  float2* bufB = bufA + M * N;
+  float2* bufB = bufA + M * PT;
   __shared__ float redf[32];
 
   const int ny = box_corner(jb.pos[2 * jn], jb.H - N, jb.status);
@@ -404,7 +409,7 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
     for (int p = 0; p < MM; ++p)
       if (p < M) {
         ps += cabs2(Pn[p]);
-        bufA[p * N + c] = cmul(Pn[p], o);
+        bufA[p * PT + c] = cmul(Pn[p], o);
       }
     pm_row = ps;
   }
@@ -416,15 +421,15 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
   }
   float2* res;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, R4, MM, 256>(bufA, M, tw);
+    fft_lds_inplace<N, false, R4, MM, 256, 0, PT, true>(bufA, M, tw);
     res = bufA;
   } else {
-    res = fft_lds<N, false, R4>(bufA, bufB, M, tw);
+    res = fft_lds<N, false, R4, 0, PT, true>(bufA, bufB, M, tw);
   }
   float2* dst = (float2*)(jb.ws + pick(L.psi, cur));
   for (int i = tid; i < M * N; i += blockDim.x) {
     const int p = i / N, cc = i - p * N;
-    dst[p * NN + (size_t)r * N + cc] = res[i];
+    dst[p * NN + (size_t)r * N + cc] = res[p * PT + cc];
   }
 }
 
@@ -451,9 +456,11 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
   constexpr int PIX = (N * CW + NT - 1) / NT;  // detector pixels per thread
   const int tid = threadIdx.x;
 
+  constexpr bool PAD = true;             // padded layout between FFT stages
+  constexpr int PT = col_pitch<N, CW, PAD>();  // LDS pitch of a transform
   float2* tw = smem;
-  float2* bufA = tw + N;                // transform (p, c) at (p * CW + c) * N
-  float2* bufB = IP ? bufA : bufA + M * CW * N;
+  float2* bufA = tw + N;                // transform (p, c) at (p * CW + c) * PT
+  float2* bufB = IP ? bufA : bufA + M * CW * PT;
   // per-wave partials of the Fourier error and of the intensity sum that
   // normalises it (kErrSlots / 256 waves per unit)
   const size_t slot = (size_t)it * kErrSlots + u * (NT / 64) + (tid >> 6);
@@ -485,16 +492,16 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
       const int k = q / CW, c = q - k * CW;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) bufA[(p * CW + c) * N + k] = v[i][p];
+        if (p < M) bufA[(p * CW + c) * PT + k] = v[i][p];
     }
   }
   __syncthreads();
   float2* F;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, R4, MM * CW, 256, 256>(bufA, M * CW, tw);
+    fft_lds_inplace<N, false, R4, MM * CW, 256, 256, PT, PAD>(bufA, M * CW, tw);
     F = bufA;
   } else {
-    F = fft_lds<N, false, R4, 256>(bufA, bufB, M * CW, tw);
+    F = fft_lds<N, false, R4, 256, PT, PAD>(bufA, bufB, M * CW, tw);
   }
   float2* G = IP ? F : ((F == bufA) ? bufB : bufA);
   // Eq. 7: the 2-D transform here is unnormalised (N x unitary) and so is
@@ -511,7 +518,7 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
       float S = 0.f;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) S += cabs2(F[(p * CW + c) * N + k]);
+        if (p < M) S += cabs2(F[(p * CW + c) * PT + k]);
       // hardware reciprocal square root and square root (about 1 ulp)
       const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
       const float Au = S * rs;
@@ -522,17 +529,17 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
       const float f = sq * rs * invN;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) G[(p * CW + c) * N + k] = cscale(F[(p * CW + c) * N + k], f);
+        if (p < M) G[(p * CW + c) * PT + k] = cscale(F[(p * CW + c) * PT + k], f);
     }
   }
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
   __syncthreads();
   float2* H;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, R4, MM * CW, 256, 256>(G, M * CW, tw);
+    fft_lds_inplace<N, true, R4, MM * CW, 256, 256, PT, PAD>(G, M * CW, tw);
     H = G;
   } else {
-    H = fft_lds<N, true, R4, 256>(G, F, M * CW, tw);
+    H = fft_lds<N, true, R4, 256, PT, PAD>(G, F, M * CW, tw);
   }
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
@@ -542,7 +549,7 @@ __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem)
       const size_t off = (size_t)k * N + u0 + c;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) psi[p * NN + off] = H[(p * CW + c) * N + k];
+        if (p < M) psi[p * NN + off] = H[(p * CW + c) * PT + k];
     }
   }
   e = wave_sum(e);
@@ -758,11 +765,11 @@ __global__ __launch_bounds__(512) void k_rows1(char* ws, float2* obj, float2* pr
   extern __shared__ float2 smem[];
   const JobRec jb{obj, probe, pos, I, ws, status, H, W, NM & 0xffff, NM >> 16, J, T};
   switch (jb.N) {
-    case 32: rows_body<32, R4, MM>(c, jb, t, smem); break;
-    case 64: rows_body<64, R4, MM>(c, jb, t, smem); break;
-    case 128: rows_body<128, R4, MM>(c, jb, t, smem); break;
-    case 192: rows_body<192, R4, MM>(c, jb, t, smem); break;
-    default: rows_body<256, R4, MM>(c, jb, t, smem); break;
+    case 32: rows_body<32, R4, MM, false, false>(c, jb, t, smem); break;
+    case 64: rows_body<64, R4, MM, false, false>(c, jb, t, smem); break;
+    case 128: rows_body<128, R4, MM, false, false>(c, jb, t, smem); break;
+    case 192: rows_body<192, R4, MM, false, false>(c, jb, t, smem); break;
+    default: rows_body<256, R4, MM, false, false>(c, jb, t, smem); break;
   }
 }
 
@@ -986,9 +993,21 @@ void set_tuning(int N, int M, int nb, const Tuning& t) {
 }
 
 // ------------------------------------------------------------ host driver
-static size_t rows_lds(int N, int M, bool inplace) { return (size_t)(N + N + (inplace ? 2 : 4) * M * N) * 8; }
-static size_t cols_lds(int N, int M, int cw, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * cw * M * N) * 8; }
-static size_t split_lds(int N, int M, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * M * N) * 8; }
+// LDS of the row passes: twiddles, the updated object row and the transforms
+// at the padded pitch col_pitch<N, 1, true>()
+static int row_pitch(int N) { return (N + N / 16 + 15) / 16 * 16; }
+static size_t rows_lds(int N, int M, bool inplace) {
+  return (size_t)(N + N + (inplace ? 2 : 4) * M * row_pitch(N)) * 8;
+}
+// LDS of the column pass: twiddles and the transforms at the padded pitch
+// col_pitch<N, cw, true>() (the one-column register-direct variant uses
+// less)
+static size_t cols_lds(int N, int M, int cw, bool inplace) {
+  const int base = (N + N / 16 + 15) / 16 * 16;
+  const int pitch = cw > 1 ? base + 16 / cw : base;
+  return (size_t)(N + (inplace ? 1 : 2) * cw * M * pitch) * 8;
+}
+static size_t split_lds(int N, int M, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * M * row_pitch(N)) * 8; }
 
 // The column pass runs in place with the row pass only in calls of this many
 // jobs or more: it doubles the workgroups per CU but adds a barrier per
