@@ -38,20 +38,20 @@ FP32_VALU_PEAK_TFS = 78.6
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "b7e5ebd3714a008e9917d59095f13b05914491f0a7109732eb7e0e2001625cac",
+    "sha256": "da9e99e75e6d5cf393872ab16e2cfcb9d9e6244c170b80747b3b7957e6b848d8",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    ("k_rows", 1): {"fetch_kib": 3460.0, "write_kib": 4097.6},
-    ("k_cols", 1): {"fetch_kib": 1000.5, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13503.6, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3720.5, "write_kib": 6160.0},
-    ("k_rows", 8): {"fetch_kib": 27353.2, "write_kib": 32780.8},
-    ("k_cols", 8): {"fetch_kib": 7315.0, "write_kib": 12320.0},
-    ("k_upd", 16): {"fetch_kib": 29138.0, "write_kib": 32865.3},
-    ("k_gat", 16): {"fetch_kib": 16715.1, "write_kib": 24832.0},
-    ("k_cols", 16): {"fetch_kib": 14557.0, "write_kib": 24640.0},
-    ("k_upd", 32): {"fetch_kib": 58194.8, "write_kib": 65730.6},
-    ("k_gat", 32): {"fetch_kib": 33356.2, "write_kib": 49664.6},
-    ("k_cols", 32): {"fetch_kib": 28934.8, "write_kib": 49295.8},
+    ("k_rows", 1): {"fetch_kib": 3459.5, "write_kib": 4097.6},
+    ("k_cols", 1): {"fetch_kib": 997.5, "write_kib": 1552.0},
+    ("k_rows", 4): {"fetch_kib": 13531.8, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3723.5, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 27341.0, "write_kib": 32780.7},
+    ("k_cols", 8): {"fetch_kib": 7318.0, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29138.7, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16727.0, "write_kib": 24832.1},
+    ("k_cols", 16): {"fetch_kib": 14539.0, "write_kib": 24640.0},
+    ("k_upd", 32): {"fetch_kib": 58196.0, "write_kib": 65730.6},
+    ("k_gat", 32): {"fetch_kib": 33369.3, "write_kib": 49664.5},
+    ("k_cols", 32): {"fetch_kib": 28916.4, "write_kib": 49434.8},
 }
 
 
