@@ -354,8 +354,9 @@ int mrpie_canvas(const mrpie_problem* pb, const void* probe, const float* pos, f
  * otherwise write the L2 back inside the timed dispatch.
  * mrpie_timing_read(avg_ms[nkinds], count[nkinds], avg_units[nkinds],
  * nkinds): waits for the recorded events, returns the mean duration, the
- * number of timed launches and the mean grid.y of those launches (jobs per
- * sweep pass, positions per adjoint pass, pairs per registration pass;
+ * number of timed launches and the mean number of units those launches
+ * process (jobs per sweep pass, positions per adjoint pass, pairs per
+ * registration pass;
  * avg_units may be NULL) per class, and clears the record.  Host-side
  * state, one per process. */
 int mrpie_timing_enable(int32_t stride);

@@ -181,82 +181,111 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
 // P4 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
 // IP: in-place transforms (one M CW N buffer instead of two, so more
 // workgroups share a CU; used while the register arrays it needs stay small)
+// The mode pass takes kAdjP4Group consecutive positions per workgroup (up to
+// four modes; one with more, where the prefetch registers would spill) and
+// loads the next position's spectra and pattern columns while the current
+// one's transforms run.
+constexpr int kAdjP4Group = 4;
+__host__ __device__ constexpr int adj_p4_group(int mm) { return mm <= 4 ? kAdjP4Group : 1; }
+
 template <int N, int MM, bool IP>
 __device__ void adj_p4(const AdjArgs& a, float2* smem) {
-  constexpr int CW = kAdjCWM, PIX = (N * CW + 255) / 256;
-  const int u = col_group(gridDim.x), b = blockIdx.y, M = a.M;
+  constexpr int CW = kAdjCWM, PIX = (N * CW + 255) / 256, GRP = adj_p4_group(MM);
+  const int u = col_group(gridDim.x), M = a.M;
   if (u >= N / CW) return;
-  const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
+  const int b0 = blockIdx.y * GRP, b1 = min(b0 + GRP, a.nb);
+  const int u0 = u * CW, tid = threadIdx.x;
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
   constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   float2* A = tw + N;          // transform (p, c) at (p * CW + c) * PT
   float2* B = IP ? A : A + M * CW * PT;
   __shared__ double redd[16];
-  float2* psi = a.Psi + (size_t)b * M * NN;
-  const float* Ij = a.I + (size_t)j * NN;
+  // pixel q = tid + 256 i of the group: row k = q / CW, column c = q % CW
+  float2 nv[PIX][MM];
+  float nI[PIX];
+  auto fetch = [&](int bb) {
+    const float2* psi = a.Psi + (size_t)bb * M * NN;
+    const float* Ij = a.I + (size_t)(a.j0 + bb) * NN;
 #pragma unroll
-  for (int i = 0; i < PIX; ++i) {
-    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
-    if (q >= N * CW) continue;
-    const size_t off = (size_t)k * N + u0 + c;
+    for (int i = 0; i < PIX; ++i) {
+      const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+      if (q >= N * CW) continue;
+      const size_t off = (size_t)k * N + u0 + c;
+      nI[i] = Ij[off];
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) A[(p * CW + c) * PT + k] = psi[p * NN + off];
-  }
+      for (int p = 0; p < MM; ++p)
+        if (p < M) nv[i][p] = psi[p * NN + off];
+    }
+  };
+  if (b0 < b1) fetch(b0);
   load_twiddles<N, kAdjThreads>(tw);
-  __syncthreads();
-  float2* F;
-  if constexpr (IP) {
-    fft_lds_inplace<N, false, false, MM * CW, 256, kAdjThreads, PT, true>(A, M * CW, tw);
-    F = A;
-  } else {
-    F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, M * CW, tw);
-  }
-  float2* G = IP ? F : ((F == A) ? B : A);  // (in place: each thread rescales the pixels it reads)
-  double e = 0.0;
   const float invN = 1.f / (float)N;
+  for (int bb = b0; bb < b1; ++bb) {
+    float Iv[PIX];
 #pragma unroll
-  for (int i = 0; i < PIX; ++i) {
-    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
-    if (q >= N * CW) continue;
-    float S = 0.f;
+    for (int i = 0; i < PIX; ++i) {
+      const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+      if (q >= N * CW) continue;
+      Iv[i] = nI[i];
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) S += cabs2(F[(p * CW + c) * PT + k]);
-    // hardware reciprocal square root and square root (about 1 ulp)
-    const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
-    const float Au = S * rs;
-    const float sq = __builtin_amdgcn_sqrtf(fmaxf(Ij[(size_t)k * N + u0 + c], 0.f));
-    const float d = Au * invN - sq;
-    e += (double)d * (double)d;
-    // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
-    // inverse 2-D transform
-    const float wgt = S > 0.f ? (1.f - sq * (float)N * rs) * invN * invN : 0.f;
+      for (int p = 0; p < MM; ++p)
+        if (p < M) A[(p * CW + c) * PT + k] = nv[i][p];
+    }
+    if (bb + 1 < b1) fetch(bb + 1);
+    lds_barrier();
+    float2* F;
+    if constexpr (IP) {
+      fft_lds_inplace<N, false, false, MM * CW, 256, kAdjThreads, PT, true>(A, M * CW, tw);
+      F = A;
+    } else {
+      F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, M * CW, tw);
+    }
+    float2* G = IP ? F : ((F == A) ? B : A);  // (in place: each thread rescales the pixels it reads)
+    double e = 0.0;
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) G[(p * CW + c) * PT + k] = cscale(F[(p * CW + c) * PT + k], wgt);
+    for (int i = 0; i < PIX; ++i) {
+      const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+      if (q >= N * CW) continue;
+      float S = 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) S += cabs2(F[(p * CW + c) * PT + k]);
+      // hardware reciprocal square root and square root (about 1 ulp)
+      const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+      const float Au = S * rs;
+      const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv[i], 0.f));
+      const float d = Au * invN - sq;
+      e += (double)d * (double)d;
+      // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
+      // inverse 2-D transform
+      const float wgt = S > 0.f ? (1.f - sq * (float)N * rs) * invN * invN : 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) G[(p * CW + c) * PT + k] = cscale(F[(p * CW + c) * PT + k], wgt);
+    }
+    lds_barrier();
+    const float2* H;
+    if constexpr (IP) {
+      fft_lds_inplace<N, true, false, MM * CW, 256, kAdjThreads, PT, true>(G, M * CW, tw);
+      H = G;
+    } else {
+      H = fft_lds<N, true, false, kAdjThreads, PT, true>(G, F, M * CW, tw);
+    }
+    float2* psi = a.Psi + (size_t)bb * M * NN;
+#pragma unroll
+    for (int i = 0; i < PIX; ++i) {
+      const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+      if (q >= N * CW) continue;
+      const size_t off = (size_t)k * N + u0 + c;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) psi[p * NN + off] = H[(p * CW + c) * PT + k];
+    }
+    e = block_sum(e, redd);  // (its barriers also end this position's reads of the LDS buffers)
+    // one partial per column group, in the slot of its first column
+    if (tid < CW) a.loss_part[(size_t)bb * N + u0 + tid] = tid == 0 ? e : 0.0;
   }
-  __syncthreads();
-  const float2* H;
-  if constexpr (IP) {
-    fft_lds_inplace<N, true, false, MM * CW, 256, kAdjThreads, PT, true>(G, M * CW, tw);
-    H = G;
-  } else {
-    H = fft_lds<N, true, false, kAdjThreads, PT, true>(G, F, M * CW, tw);
-  }
-#pragma unroll
-  for (int i = 0; i < PIX; ++i) {
-    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
-    if (q >= N * CW) continue;
-    const size_t off = (size_t)k * N + u0 + c;
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + off] = H[(p * CW + c) * PT + k];
-  }
-  e = block_sum(e, redd);
-  // one partial per column group, in the slot of its first column
-  if (tid < CW) a.loss_part[(size_t)b * N + u0 + tid] = tid == 0 ? e : 0.0;
 }
 
 // P5 (rows): chi row r; g = 2 sum_p conj(P_p) chi_p, row FFT.  A workgroup
@@ -285,16 +314,33 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
     if (p < M && c < N) P[p] = a.probe[p * NN + roff];
   }
   load_twiddles<N, kAdjThreads>(tw);
+  // software pipeline: the next position's spectra row and patch row are
+  // loaded into registers while this position's transforms run (the LDS
+  // barriers of the transforms leave those loads in flight)
+  float2 nv[MM], no = make_float2(0.f, 0.f);
+  if (c < N && b0 < b1) {
+    const float2* psi0 = a.Psi + (size_t)b0 * M * NN;
+    no = a.Cp[chunk_off(b0, N) + roff];
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) nv[p] = psi0[p * NN + roff];
+  }
   for (int b = b0; b < b1; ++b) {
-    float2* psi = a.Psi + (size_t)b * M * NN;
     float2 o = make_float2(0.f, 0.f);
     if (c < N) {
-      o = a.Cp[chunk_off(b, N) + roff];
+      o = no;
 #pragma unroll
       for (int p = 0; p < MM; ++p)
-        if (p < M) A[p * PT + c] = psi[p * NN + roff];
+        if (p < M) A[p * PT + c] = nv[p];
+      if (b + 1 < b1) {
+        const float2* psin = a.Psi + (size_t)(b + 1) * M * NN;
+        no = a.Cp[chunk_off(b + 1, N) + roff];
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) nv[p] = psin[p * NN + roff];
+      }
     }
-    __syncthreads();
+    lds_barrier();
     float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, M, tw);
     float2* W = (R == A) ? B : A;
     if (c < N) {
@@ -308,10 +354,10 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
         }
       W[c] = cscale(g, 2.f);
     }
-    __syncthreads();
+    lds_barrier();
     float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, 1, tw);
     if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
-    __syncthreads();  // A, B are reused by the next position
+    lds_barrier();  // A, B are reused by the next position
   }
   if (c < N) {
     float2* part = a.Psi + (size_t)b0 * M * NN;
@@ -595,16 +641,17 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   MRPIE_HIP(ensure_lds((const void*)k_adj_p2, lc1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p6, lc1));
   const auto kp4 = M <= 1 ? k_adj_p4<1> : M <= 2 ? k_adj_p4<2> : M <= 4 ? k_adj_p4<4> : k_adj_p4<MRPIE_MAX_MODES>;
+  const int g4 = adj_p4_group(M <= 4 ? 4 : MRPIE_MAX_MODES);  // positions per workgroup of k_adj_p4
   MRPIE_HIP(ensure_lds((const void*)kp4, lcm));
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     a.nb = nb;
-    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), gm(N / kAdjCWM, nb), blk(kAdjThreads);
+    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), blk(kAdjThreads);
     hipLaunchKernelGGL(k_adj_p1, gr, blk, l1, s, a);
     hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
     hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
-    launch_k(TK_ADJ, kp4, gm, blk, lcm, s, a);
+    launch_ku(TK_ADJ, nb, kp4, dim3(N / kAdjCWM, (nb + g4 - 1) / g4), blk, lcm, s, a);  // timed per position
     hipLaunchKernelGGL(k_adj_loss_part, dim3(kLossBlocks), blk, 0, s, a, nb);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(kLossBlocks), 0, s, a);
     if (grads) {

@@ -119,9 +119,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ float block_max(float v, float* red) {
   v = wave_max(v);
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
+  lds_barrier();
   if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
+  lds_barrier();
   float r = red[0];
   for (int i = 1; i < nw; ++i) r = fmaxf(r, red[i]);
   return r;
@@ -132,12 +132,12 @@ __device__ __forceinline__ void block_max2(float a, float b, float* red, float& 
   a = wave_max(a);
   b = wave_max(b);
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
+  lds_barrier();
   if ((threadIdx.x & 63) == 0) {
     red[w] = a;
     red[16 + w] = b;
   }
-  __syncthreads();
+  lds_barrier();
   ra = red[0];
   rb = red[16];
   for (int i = 1; i < nw; ++i) {
@@ -149,9 +149,9 @@ __device__ __forceinline__ void block_max2(float a, float b, float* red, float& 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
+  lds_barrier();
   if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
+  lds_barrier();
   double r = 0.0;
   for (int i = 0; i < nw; ++i) r += red[i];
   return r;
@@ -209,11 +209,18 @@ struct TimedLaunch {
 // adjoint pass, pairs of a registration pass), averaged per class.
 TimedLaunch timing_slot(int kind, int units);
 
+// units: what the timing record averages for this launch (jobs, positions
+// or pairs it processes)
 template <typename K, typename... A>
-inline void launch_k(int kind, K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
-  const TimedLaunch t = timing_slot(kind, (int)grid.y);
+inline void launch_ku(int kind, int units, K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+  const TimedLaunch t = timing_slot(kind, units);
   if (t.start) hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, t.start, t.stop, 0u, args...);
   else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+// ... with grid.y units
+template <typename K, typename... A>
+inline void launch_k(int kind, K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args) {
+  launch_ku(kind, (int)grid.y, kernel, grid, block, lds, s, args...);
 }
 
 }  // namespace mrpie

@@ -130,6 +130,19 @@ template <> struct Plan4<128> { static constexpr int R[4] = {4, 4, 4, 2}; };
 template <> struct Plan4<192> { static constexpr int R[4] = {4, 4, 4, 3}; };
 template <> struct Plan4<256> { static constexpr int R[4] = {4, 4, 4, 4}; };
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// orders global memory, which on gfx9 means waiting for every outstanding
+// global load and store of the wave (one counter covers both); the FFT
+// stages and the block reductions only exchange data through LDS, so with
+// this barrier stores issued before a transform drain while it runs and
+// loads issued for later use stay in flight.  Code that hands global memory
+// from one wave to another must still use __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Threads per workgroup: NT when the caller's kernel has a fixed size,
 // else blockDim.x.  (blockDim.x is read from the implicit kernel arguments
 // with a vector load and a wait on every outstanding load, each time a
@@ -192,8 +205,8 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
 
 // Full N-point transforms of `nb` contiguous rows in LDS buffer `a`, using
 // `b` as the ping-pong partner.  Returns the buffer holding the result.
-// Callers must __syncthreads() before (data ready); the result is ready on
-// return (a barrier ends every stage).  NT: the kernel's fixed workgroup
+// Callers must synchronise before (data ready in LDS); the result is ready
+// on return (an LDS barrier ends every stage).  NT: the kernel's fixed workgroup
 // size (0: read blockDim.x); PITCH: transform b starts at element b * PITCH;
 // PAD: padded layout between stages (PITCH >= padded_len<N>()).
 template <int N, bool INV, bool R4 = true, int NT = 0, int PITCH = N, bool PAD = false, typename C>
@@ -201,15 +214,15 @@ __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
   using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
   constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
   stage<N, R0, 1, INV, NT, PITCH, false, PAD>(a, b, nb, tw);
-  __syncthreads();
+  lds_barrier();
   stage<N, R1, R0, INV, NT, PITCH, PAD, PAD && (R2 > 1)>(b, a, nb, tw);
-  __syncthreads();
+  lds_barrier();
   if constexpr (R2 == 1) return a;
   stage<N, R2, R0 * R1, INV, NT, PITCH, PAD, PAD && (R3 > 1)>(a, b, nb, tw);
-  __syncthreads();
+  lds_barrier();
   if constexpr (R3 == 1) return b;
   stage<N, R3, R0 * R1 * R2, INV, NT, PITCH, PAD, false>(b, a, nb, tw);
-  __syncthreads();
+  lds_barrier();
   return a;
 }
 
@@ -240,7 +253,7 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
       for (int r = 0; r < R; ++r) v[i][r] = buf[b * PITCH + (PIN ? pad16(j + r * Q) : j + r * Q)];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int t = threadIdx.x + i * wg_threads<NT>();
@@ -261,7 +274,7 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
       for (int r = 0; r < R; ++r) buf[bs[i] + (POUT ? pad16(o + r * NS) : o + r * NS)] = v[i][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Full in-place transforms of `nb` (<= MAXNB) contiguous rows of `buf`

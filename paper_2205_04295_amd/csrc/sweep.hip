@@ -230,7 +230,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
       }
     }
     if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
-    __syncthreads();
+    lds_barrier();  // publishes orow; the probe and object stores drain meanwhile
   } else {
 #pragma unroll
     for (int p = 0; p < MM; ++p)
