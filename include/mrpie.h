@@ -205,8 +205,9 @@ typedef struct {
  * M <= lds_sweep whose modes fit the LDS together (M N^2 <= 16384: 32^2
  * with up to 8 modes, 64^2 with up to 4, 128^2 with 1) runs as one
  * workgroup that keeps the probe in registers and the 2-D FFT in LDS for
- * the whole call; other jobs run the row / column passes (default: 8 for
- * N = 32, 1 for N = 64, 0 otherwise); cols_width: 1 or 4 adjacent detector
+ * the whole call; other jobs run the row / column passes (default for
+ * single-job calls: 8 for N = 32, 1 for N = 64, 0 otherwise; 0 in batches,
+ * where small jobs ride along in the shared launches); cols_width: 1 or 4 adjacent detector
  * columns per column-pass workgroup (1: shortest latency for a single
  * sweep; 4: coalesced 32-byte row segments, for batches); rows_inplace: 1
  * runs the inverse row FFTs of multi-job launches in place (half the row

@@ -969,9 +969,16 @@ static int batch_class(int nb) { return nb <= 1 ? 0 : nb < kLargeBatch ? 1 : 2; 
 int batch_class_jobs(int cls) { return cls <= 0 ? 1 : cls == 1 ? 2 : kLargeBatch; }
 static int mode_index(int M) { return M <= 1 ? 0 : M <= 2 ? 1 : M <= 4 ? 2 : 3; }
 
+// The one-workgroup LDS sweep is the default for a single small job only: in
+// a batch, small jobs ride along in the shared row / column launches, which
+// the other jobs' launches pay for anyway (uneven 64-job batch: 439k -> 480k
+// positions x iterations / s eager, 310k -> 337k as a replayed graph, where
+// the LDS sweep's long single launch would otherwise run ahead of the passes
+// on the one stream).
 Tuning default_tuning(int N, int nb) {
   const int bc = batch_class(nb);
-  return Tuning{8, 8, 256, N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0, bc ? 4 : 1, bc ? 1 : 0, bc == 2 ? 1 : 0};
+  const int lds = bc ? 0 : N == 32 ? MRPIE_MAX_MODES : N == 64 ? 1 : 0;
+  return Tuning{8, 8, 256, lds, bc ? 4 : 1, bc ? 1 : 0, bc == 2 ? 1 : 0};
 }
 
 Tuning get_tuning(int N, int M, int nb) {

@@ -145,6 +145,8 @@ def test_tuning_round_trip(lib):
     assert (d0.cols_width, d0.rows_inplace, d0.rows_split) == (1, 0, 0)
     d64 = _abi.Tuning()
     assert lib.mrpie_get_tuning(64, 1, 0, C.byref(d64)) == 0 and d64.lds_sweep == 1
+    for cls in (1, 2):  # batches run small jobs through the shared passes by default
+        assert lib.mrpie_get_tuning(64, 1, cls, C.byref(d64)) == 0 and d64.lds_sweep == 0
     d32 = _abi.Tuning()
     assert lib.mrpie_get_tuning(32, 5, 0, C.byref(d32)) == 0 and d32.lds_sweep == 8
     # per mode class: setting M = 3 changes the class of M = 3-4 only
