@@ -264,7 +264,9 @@ def measure_refine(api, torch, dev, args):
     iterations / s and the position RMS error vs the truth before / after,
     at the configured upsampling factor 100 and, as a second run, at 1000
     (the registered shifts between a patch and its update are mostly below
-    the 0.01 px lag spacing of factor 100)."""
+    the 0.01 px lag spacing of factor 100); a third run registers at the
+    paper's other point, XCORR_B (the modelled detector amplitude against
+    the measured one), at upsample 1000."""
     import numpy as np
     from synth import workloads as wl
     t0 = time.time()
@@ -278,7 +280,7 @@ def measure_refine(api, torch, dev, args):
         return float(np.sqrt(np.mean(np.sum(d * d, axis=1)))), \
             float(np.sqrt(np.mean(np.sum((d - d.mean(0)) ** 2, axis=1))))
 
-    def run(up):
+    def run(up, xcorr_point=0):
         obj = torch.from_numpy(w.O0).to(dev)
         probe = torch.from_numpy(w.P0).to(dev)
         pos = torch.from_numpy(w.pos0).to(dev)
@@ -287,6 +289,7 @@ def measure_refine(api, torch, dev, args):
         prm = dict(w.params)
         prm.pop("iterations", None)
         prm["upsample"] = up
+        prm["xcorr_point"] = xcorr_point
         ws = None
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -300,6 +303,9 @@ def measure_refine(api, torch, dev, args):
 
     el, after, moved = run(100)
     el2, after2, moved2 = run(1000)
+    # the paper's other registration point (XCORR_B: modelled detector
+    # amplitude against sqrt(I)) on the same workload, upsample 1000
+    el3, after3, moved3 = run(1000, xcorr_point=1)
     return {"workload": "spiral256x3 with N(0, 3 px) position errors, subpixel Fourier moves, XCORR_A "
                         "registration (upsample 100, unnormalised cross-power) + Adam (lr 0.5) every iteration",
             "iterations": T, "value": round(J * T / el, 1), "unit": "positions*iter/s",
@@ -308,6 +314,8 @@ def measure_refine(api, torch, dev, args):
             "pos_rms_px_after": after, "rms_note": "[raw, mean-offset removed]", "positions_moved_frac": moved,
             "upsample_1000": {"value": round(J * T / el2, 1), "pos_rms_px_after": after2,
                               "positions_moved_frac": moved2},
+            "xcorr_b_upsample_1000": {"value": round(J * T / el3, 1), "pos_rms_px_after": after3,
+                                      "positions_moved_frac": moved3},
             "datagen_s": round(gen, 1)}
 
 
