@@ -25,10 +25,14 @@
 // reads the object after position s-1 has written it.
 //
 // Batching: blockIdx.y selects a job from the launch's job table; every job
-// advances one position per launch pair (lock-step), so many independent
+// advances one position per tick (lock-step), so many independent
 // reconstructions of different N, M, J fill the GPU that one sweep cannot.
-// Every global load a workgroup needs is issued at kernel start, before the
-// first LDS stage, so each launch pays one memory latency.
+// Batches of 16 or more jobs (by default) split the row work into two
+// launches, k_upd (the update of step s-1) and k_gat (the gather of step
+// s), which read every row of the spectra once and keep no patch copy (see
+// the split passes below).  Every global load a workgroup needs is issued at
+// kernel start, before the first LDS stage, so each launch pays one memory
+// latency; the LDS barriers of the transforms leave global stores draining.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -44,9 +48,12 @@ __device__ __forceinline__ size_t pick(const size_t (&a)[2], int i) { return i ?
 
 // IP: the inverse row FFTs run in place (one 3MN buffer instead of two:
 // more workgroups per CU, one more barrier per stage) — for batches.
-// PAD: padded layout between FFT stages (fewer LDS bank conflicts: pays in
-// batches; a single job's latency chain only sees its extra index arithmetic)
-template <int N, bool R4, int MM, bool IP = false, bool PAD = true>
+// SINGLE: the single-job launch.  Batches use the padded layout between FFT
+// stages (fewer LDS bank conflicts; a single job's latency chain would only
+// see its extra index arithmetic), and only a single job touches the next
+// pattern row early (a prefetch for its latency-bound column pass; in a
+// batch, which is bound by memory traffic, it would be a second read).
+template <int N, bool R4, int MM, bool IP = false, bool SINGLE = false>
 __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
   const int M = jb.M;
   const int total = jb.J * jb.T;
@@ -61,6 +68,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   const int tid = threadIdx.x;
   const bool lane = tid < N;  // this thread owns column `tid`
 
+  constexpr bool PAD = !SINGLE;
   constexpr int PT = col_pitch<N, 1, PAD>();  // LDS pitch of a transform
   float2* tw = smem;               // N
   float2* orow = tw + N;           // N   updated object row (box-prev row rb1)
@@ -103,7 +111,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     }
     // touch row r of this step's pattern so the column pass that follows
     // finds it in the memory-side cache instead of HBM
-    if (has_next) i_touch = jb.I[(size_t)jn * NN + off];
+    if (SINGLE && has_next) i_touch = jb.I[(size_t)jn * NN + off];
   }
 
   // ---- box geometry
@@ -268,7 +276,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     const int p = i / N, cc = i - p * N;
     dst[p * NN + (size_t)r * N + cc] = res[p * PT + cc];
   }
-  if (i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
+  if (SINGLE && i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
 
 // Split row passes for batches (three launches per position: update rows,
@@ -765,11 +773,11 @@ __global__ __launch_bounds__(512) void k_rows1(char* ws, float2* obj, float2* pr
   extern __shared__ float2 smem[];
   const JobRec jb{obj, probe, pos, I, ws, status, H, W, NM & 0xffff, NM >> 16, J, T};
   switch (jb.N) {
-    case 32: rows_body<32, R4, MM, false, false>(c, jb, t, smem); break;
-    case 64: rows_body<64, R4, MM, false, false>(c, jb, t, smem); break;
-    case 128: rows_body<128, R4, MM, false, false>(c, jb, t, smem); break;
-    case 192: rows_body<192, R4, MM, false, false>(c, jb, t, smem); break;
-    default: rows_body<256, R4, MM, false, false>(c, jb, t, smem); break;
+    case 32: rows_body<32, R4, MM, false, true>(c, jb, t, smem); break;
+    case 64: rows_body<64, R4, MM, false, true>(c, jb, t, smem); break;
+    case 128: rows_body<128, R4, MM, false, true>(c, jb, t, smem); break;
+    case 192: rows_body<192, R4, MM, false, true>(c, jb, t, smem); break;
+    default: rows_body<256, R4, MM, false, true>(c, jb, t, smem); break;
   }
 }
 
