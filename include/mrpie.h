@@ -259,8 +259,9 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
  * 16 or more: the two classes of mrpie_rpie_batched calls).  mrpie_autotune fills its workspace with `batch`
  * synthetic problems of shape (N, M, J positions, object 3N x 3N), runs one
  * sweep iteration with every candidate (mrpie_tuning_candidates lists them,
- * in order) reps + 1 times on `stream` (the first run warms up), timed with
- * HIP events, keeps each candidate's fastest timed run, installs the best
+ * in order) in reps + 1 round-robin rounds on `stream` (the first round warms
+ * up), timed with HIP events, keeps each candidate's fastest timed run,
+ * installs the best
  * candidate for that (N, mode class, batch class) as mrpie_set_tuning
  * would, and returns it in *best (may be NULL).  cand_ms (may be NULL)
  * receives each candidate's time in ms.  The call waits on the host for its

@@ -58,7 +58,7 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
   const int M = jb.M;
   const int total = jb.J * jb.T;
   const int r = blockIdx.x;
-  if (t > total || r >= N) return;
+  if (t < 0 || t > total || r >= N) return;
   const bool has_prev = t > 0, has_next = t < total;
   const int cur = t & 1, prv = (t + 1) & 1;
   const int jn = has_next ? t % jb.J : 0;
@@ -386,7 +386,7 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
   const int M = jb.M;
   const int total = jb.J * jb.T;
   const int r = blockIdx.x;
-  if (t >= total || r >= N) return;
+  if (t < 0 || t >= total || r >= N) return;
   const int cur = t & 1, jn = t % jb.J;
   const WsLayout L = ws_layout(N, M, jb.T);
   const size_t NN = (size_t)N * N;
@@ -451,7 +451,7 @@ template <int N, bool R4, int MM, int CW, bool IP = false>
 __device__ __forceinline__ void cols_body(const JobRec& jb, int t, float2* smem) {
   const int M = jb.M;
   const int total = jb.J * jb.T;
-  if (t >= total) return;
+  if (t < 0 || t >= total) return;
   const int u = xcd_unit(blockIdx.x, gridDim.x);  // column group of this workgroup
   if (u >= N / CW) return;
   const int u0 = u * CW;
@@ -585,7 +585,7 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
   constexpr int QL = N / RL;       // threads of the mode-sum stage
   const int M = jb.M;
   const int total = jb.J * jb.T;
-  if (t >= total) return;
+  if (t < 0 || t >= total) return;
   const int u = xcd_unit(blockIdx.x, gridDim.x);
   if (u >= N) return;
   const int it = t / jb.J, jn = t - it * jb.J;
@@ -700,11 +700,14 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
 
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
 // (jobs of the launch have M <= MM), so small M does not pay the register
-// cost (and occupancy) of the largest.
+// cost (and occupancy) of the largest.  `tg` is the launch tick; a job runs
+// its own step tg - t0 (t0 = 0 unless the job waited for an earlier job of
+// its launch lane).
 template <bool R4, int MM, bool IP>
-__global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
+__global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int tg) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
+  const int t = tg - jb.t0;
   switch (jb.N) {
     case 32: rows_body<32, R4, MM, IP>(a.c, jb, t, smem); break;
     case 64: rows_body<64, R4, MM, IP>(a.c, jb, t, smem); break;
@@ -715,9 +718,10 @@ __global__ __launch_bounds__(512) void k_rows(const LaunchArgs a, int t) {
 }
 
 template <bool R4, int MM, bool IP>
-__global__ __launch_bounds__(512) void k_upd(const LaunchArgs a, int t) {
+__global__ __launch_bounds__(512) void k_upd(const LaunchArgs a, int tg) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
+  const int t = tg - jb.t0;
   switch (jb.N) {
     case 32: upd_body<32, R4, MM, IP>(a.c, jb, t, smem); break;
     case 64: upd_body<64, R4, MM, IP>(a.c, jb, t, smem); break;
@@ -728,9 +732,10 @@ __global__ __launch_bounds__(512) void k_upd(const LaunchArgs a, int t) {
 }
 
 template <bool R4, int MM, bool IP>
-__global__ __launch_bounds__(512) void k_gat(const LaunchArgs a, int t) {
+__global__ __launch_bounds__(512) void k_gat(const LaunchArgs a, int tg) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
+  const int t = tg - jb.t0;
   switch (jb.N) {
     case 32: gat_body<32, R4, MM, IP>(jb, t, smem); break;
     case 64: gat_body<64, R4, MM, IP>(jb, t, smem); break;
@@ -741,9 +746,10 @@ __global__ __launch_bounds__(512) void k_gat(const LaunchArgs a, int t) {
 }
 
 template <bool R4, int MM, int CW, bool IP>
-__global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int t) {
+__global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int tg) {
   extern __shared__ float2 smem[];
   const JobRec& jb = a.job[blockIdx.y];
+  const int t = tg - jb.t0;
   constexpr bool RD = !R4 && CW == 1 && !IP;
   switch (jb.N) {
     case 32: cols_body<32, R4, MM, CW, IP>(jb, t, smem); break;
@@ -1042,55 +1048,98 @@ void launch_finish(const LaunchArgs& a, int nb, float* const* err_out, hipStream
   hipLaunchKernelGGL(k_finish, dim3(1, nb), dim3(256), 0, s, a, eo);
 }
 
-// One launch group: up to kMaxJobsPerLaunch jobs that share every launch
-// (a single-job call takes the scalar-argument kernels).
+// One launch group: the jobs of one stream that share every launch (a
+// single-job call takes the scalar-argument kernels).  The jobs are dealt to
+// at most kMaxJobsPerLaunch lanes: the longest first, each to the lane that
+// frees up first, where it starts one tick after the lane's previous job
+// took its last update.  Every tick's launches carry the jobs the lanes are
+// running at that tick, so a launch never exceeds kMaxJobsPerLaunch jobs and
+// carries no finished job, and the short jobs of an uneven batch queue
+// behind each other in the lanes instead of taking launches of their own.
 struct PassGroup {
-  LaunchArgs a{};
-  ErrOut eo{};
-  int nb = 0, maxN = 64, maxTot = 0, width = 1;
+  LaunchArgs a{};  // single-job calls: the job
+  int maxTot = 0;  // last tick of the group
   bool single = false;  // a single-job call: the scalar-argument kernels
   bool split = false;   // update / gather / column launches per position
+  int width = 1;
   size_t lr = 0, lc = 0, lu = 0;
   dim3 rblk;
   SweepKernel kr = nullptr, kc = nullptr, ku = nullptr, kg = nullptr;
   RowsKernel1 kr1 = nullptr;
   ColsKernel1 kc1 = nullptr;
   hipStream_t s = nullptr;
+  std::vector<JobRec> jobs;             // every job of the group, start ticks set
+  std::vector<float*> err;
+  std::vector<std::vector<int>> lanes;  // the jobs of each lane, in start order
+  std::vector<size_t> cur;              // per lane: its current job
 };
+
+static long long job_ticks(const JobRec& jb) { return (long long)jb.J * jb.T; }
+
+// Deal the jobs to the lanes and set their start ticks.
+static int deal_lanes(PassGroup& g) {
+  const int n = (int)g.jobs.size();
+  const int nl = std::min(n, kMaxJobsPerLaunch);
+  std::vector<int> order(n);
+  for (int b = 0; b < n; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return job_ticks(g.jobs[x]) > job_ticks(g.jobs[y]); });
+  std::vector<long long> load(nl, 0);
+  g.lanes.assign(nl, {});
+  g.cur.assign(nl, 0);
+  long long last = 0;
+  for (int b : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    const long long tot = job_ticks(g.jobs[b]);
+    if (tot == 0) continue;  // no iterations: nothing to launch
+    g.jobs[b].t0 = (int)load[l];
+    load[l] += tot + 1;      // job ticks 0 .. tot
+    if (load[l] > INT32_MAX) return fail(MRPIE_EINVAL, "batched call: a launch lane exceeds 2^31 ticks");
+    last = std::max(last, load[l] - 1);
+    g.lanes[l].push_back(b);
+  }
+  g.maxTot = (int)last;
+  return MRPIE_OK;
+}
 
 // `call_jobs` (the jobs of the whole call) picks the tuning class and the
 // kernels, so a job computes the same bits whichever group and stream it is
 // dealt to.
 static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* jobs, float* const* err, int nb,
                          int call_jobs, hipStream_t s, const Tuning* force) {
-  g.a.c = c;
-  g.a.njobs = nb;
-  g.nb = nb;
   g.s = s;
-  int maxM = 1;
+  int maxN = 64, maxM = 1;
   for (int b = 0; b < nb; ++b) {
-    g.a.job[b] = *jobs[b];
-    g.maxN = std::max(g.maxN, jobs[b]->N);
-    g.maxTot = std::max(g.maxTot, jobs[b]->J * jobs[b]->T);
+    g.jobs.push_back(*jobs[b]);
+    g.jobs.back().t0 = 0;
+    g.err.push_back(err[b]);
+    maxN = std::max(maxN, jobs[b]->N);
     maxM = std::max(maxM, jobs[b]->M);
-    g.eo.p[b] = err[b];
   }
-  const Tuning tu = force ? *force : get_tuning(g.maxN, maxM, call_jobs);
+  const Tuning tu = force ? *force : get_tuning(maxN, maxM, call_jobs);
   const bool ip = call_jobs > 1 && tu.rows_inplace;
   const bool cip = ip && tu.cols_width == 4 && call_jobs >= kColsInplaceJobs;
-  for (int b = 0; b < nb; ++b) g.lr = std::max(g.lr, rows_lds(g.a.job[b].N, g.a.job[b].M, ip));
-  for (int b = 0; b < nb; ++b) g.lc = std::max(g.lc, cols_lds(g.a.job[b].N, g.a.job[b].M, tu.cols_width, cip));
+  for (const JobRec& jb : g.jobs) g.lr = std::max(g.lr, rows_lds(jb.N, jb.M, ip));
+  for (const JobRec& jb : g.jobs) g.lc = std::max(g.lc, cols_lds(jb.N, jb.M, tu.cols_width, cip));
   g.width = tu.cols_width;
   g.rblk = dim3(tu.rows_threads);
   g.single = call_jobs == 1;
   if (g.single) {
-    g.kr1 = rows_kernel1(tu.rows_radix, g.a.job[0].M);
-    g.kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, g.a.job[0].M);
+    g.a.c = c;
+    g.a.njobs = 1;
+    g.a.job[0] = g.jobs[0];
+    g.maxTot = (int)job_ticks(g.jobs[0]);
+    g.kr1 = rows_kernel1(tu.rows_radix, g.jobs[0].M);
+    g.kc1 = cols_kernel1(tu.cols_radix, tu.cols_width, g.jobs[0].M);
     MRPIE_HIP(ensure_lds((const void*)g.kr1, g.lr));
     MRPIE_HIP(ensure_lds((const void*)g.kc1, g.lc));
-  } else if (tu.rows_split) {
+    return MRPIE_OK;
+  }
+  const int rc = deal_lanes(g);
+  if (rc) return rc;
+  if (tu.rows_split) {
     g.split = true;
-    for (int b = 0; b < nb; ++b) g.lu = std::max(g.lu, split_lds(g.a.job[b].N, g.a.job[b].M, ip));
+    for (const JobRec& jb : g.jobs) g.lu = std::max(g.lu, split_lds(jb.N, jb.M, ip));
     g.ku = upd_kernel(tu.rows_radix, ip, maxM);
     g.kg = gat_kernel(tu.rows_radix, ip, maxM);
     g.kc = cols_kernel(tu.cols_radix, tu.cols_width, cip, maxM);
@@ -1106,41 +1155,99 @@ static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* job
   return MRPIE_OK;
 }
 
+// The job tables of tick t: `all` the jobs running (their steps 0 .. J T),
+// `upd` those with a previous step to update (1 .. J T), `nxt` those with a
+// step to gather (0 .. J T - 1).  Largest probe size of each in *_n.
+struct TickTables {
+  LaunchArgs all, upd, nxt;
+  int all_n = 0, upd_n = 0, nxt_n = 0;
+};
+
+static void tick_tables(PassGroup& g, const Common& c, int t, TickTables& tt) {
+  tt.all.c = tt.upd.c = tt.nxt.c = c;
+  int na = 0, nu = 0, nn = 0;
+  for (size_t l = 0; l < g.lanes.size(); ++l) {
+    const std::vector<int>& q = g.lanes[l];
+    size_t& k = g.cur[l];
+    while (k < q.size() && g.jobs[q[k]].t0 + job_ticks(g.jobs[q[k]]) < t) ++k;
+    if (k == q.size() || g.jobs[q[k]].t0 > t) continue;
+    const JobRec& jb = g.jobs[q[k]];
+    const long long lt = t - jb.t0;
+    tt.all.job[na++] = jb;
+    tt.all_n = std::max(tt.all_n, jb.N);
+    if (lt > 0) {
+      tt.upd.job[nu++] = jb;
+      tt.upd_n = std::max(tt.upd_n, jb.N);
+    }
+    if (lt < job_ticks(jb)) {
+      tt.nxt.job[nn++] = jb;
+      tt.nxt_n = std::max(tt.nxt_n, jb.N);
+    }
+  }
+  tt.all.njobs = na;
+  tt.upd.njobs = nu;
+  tt.nxt.njobs = nn;
+}
+
 // tick t of a group: the (t-1 -> t) row pass and the column pass of step t
-static void launch_tick(const PassGroup& g, const Common& c, int t) {
+static void launch_tick(PassGroup& g, const Common& c, int t) {
   const dim3 blk(256);
   if (g.single) {
     const JobRec& jb = g.a.job[0];
     const int NM = jb.N | (jb.M << 16);
-    launch_k(TK_ROWS, g.kr1, dim3(g.maxN, 1), g.rblk, g.lr, g.s, jb.ws, jb.obj, jb.probe, jb.pos, t, jb.J, jb.T, NM,
+    launch_k(TK_ROWS, g.kr1, dim3(jb.N, 1), g.rblk, g.lr, g.s, jb.ws, jb.obj, jb.probe, jb.pos, t, jb.J, jb.T, NM,
              jb.H, jb.W, jb.I, jb.status, c);
     if (t < g.maxTot)
-      launch_k(TK_COLS, g.kc1, dim3(g.maxN / g.width, 1), blk, g.lc, g.s, jb.ws, jb.I, t, jb.J, jb.T, NM, jb.status);
+      launch_k(TK_COLS, g.kc1, dim3(jb.N / g.width, 1), blk, g.lc, g.s, jb.ws, jb.I, t, jb.J, jb.T, NM, jb.status);
     return;
   }
+  TickTables tt;
+  tick_tables(g, c, t, tt);
   if (g.split) {
-    if (t > 0) launch_k(TK_UPD, g.ku, dim3(g.maxN, g.nb), g.rblk, g.lu, g.s, g.a, t);
-    if (t < g.maxTot) {
-      launch_k(TK_GAT, g.kg, dim3(g.maxN, g.nb), g.rblk, g.lu, g.s, g.a, t);
-      launch_k(TK_COLS, g.kc, dim3(g.maxN / g.width, g.nb), blk, g.lc, g.s, g.a, t);
+    if (tt.upd.njobs) launch_k(TK_UPD, g.ku, dim3(tt.upd_n, tt.upd.njobs), g.rblk, g.lu, g.s, tt.upd, t);
+    if (tt.nxt.njobs) {
+      launch_k(TK_GAT, g.kg, dim3(tt.nxt_n, tt.nxt.njobs), g.rblk, g.lu, g.s, tt.nxt, t);
+      launch_k(TK_COLS, g.kc, dim3(tt.nxt_n / g.width, tt.nxt.njobs), blk, g.lc, g.s, tt.nxt, t);
     }
     return;
   }
-  launch_k(TK_ROWS, g.kr, dim3(g.maxN, g.nb), g.rblk, g.lr, g.s, g.a, t);
-  if (t < g.maxTot) launch_k(TK_COLS, g.kc, dim3(g.maxN / g.width, g.nb), blk, g.lc, g.s, g.a, t);
+  if (tt.all.njobs) launch_k(TK_ROWS, g.kr, dim3(tt.all_n, tt.all.njobs), g.rblk, g.lr, g.s, tt.all, t);
+  if (tt.nxt.njobs) launch_k(TK_COLS, g.kc, dim3(tt.nxt_n / g.width, tt.nxt.njobs), blk, g.lc, g.s, tt.nxt, t);
+}
+
+// The per-job launches before and after the passes (error partials cleared;
+// the final probe copied back, the errors reduced), kMaxJobsPerLaunch jobs
+// at a time.
+static void launch_group_edges(const PassGroup& g, const Common& c, bool after) {
+  if (g.single) {
+    if (!after) hipLaunchKernelGGL(k_zero_err, dim3(8, 1), dim3(256), 0, g.s, g.a);
+    else launch_finish(g.a, 1, g.err.data(), g.s, true);
+    return;
+  }
+  const int n = (int)g.jobs.size();
+  for (int c0 = 0; c0 < n; c0 += kMaxJobsPerLaunch) {
+    const int nb = std::min(kMaxJobsPerLaunch, n - c0);
+    LaunchArgs a{};
+    a.c = c;
+    a.njobs = nb;
+    for (int b = 0; b < nb; ++b) a.job[b] = g.jobs[c0 + b];
+    // (the split passes update the probe in place: nothing to copy back)
+    if (!after) hipLaunchKernelGGL(k_zero_err, dim3(8, nb), dim3(256), 0, g.s, a);
+    else launch_finish(a, nb, g.err.data() + c0, g.s, !g.split);
+  }
 }
 
 // Row / column passes, lock-step over the jobs.  With a second stream `s2`
 // (already forked from `s`) the jobs are dealt alternately to the two
-// streams; each stream's share is cut into launch groups, and the launches
-// of all groups are issued tick by tick.  A launch of a few jobs leaves most
-// of the GPU idle while it waits on memory, so the other stream's launches
-// fill it (measured at 256^2 x 3: 8 jobs 198k -> 219k, 32 jobs 266k -> 287k
+// streams, one launch group each, and the launches of both groups are
+// issued tick by tick.  A launch of a few jobs leaves most of the GPU idle
+// while it waits on memory, so the other stream's launches fill it
+// (measured at 256^2 x 3: 8 jobs 198k -> 219k, 32 jobs 266k -> 287k
 // positions x iterations / s; four streams gained less than two).
 static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* const* err_out, hipStream_t s,
                       hipStream_t s2, const Tuning* force) {
   const int ns = s2 ? 2 : 1;
-  std::vector<PassGroup> groups;
+  std::vector<PassGroup> groups(ns);
   for (int k = 0; k < ns; ++k) {
     std::vector<const JobRec*> js;
     std::vector<float*> es;
@@ -1148,27 +1255,18 @@ static int run_passes(const Common& c, const JobRec* jobs, int njobs, float* con
       js.push_back(&jobs[b]);
       es.push_back(err_out ? err_out[b] : nullptr);
     }
-    const int n = (int)js.size();
-    for (int c0 = 0; c0 < n; c0 += kMaxJobsPerLaunch) {
-      groups.emplace_back();
-      const int rc = prepare_group(groups.back(), c, js.data() + c0, es.data() + c0,
-                                   std::min(kMaxJobsPerLaunch, n - c0), njobs, k == 0 ? s : s2, force);
-      if (rc) return rc;
-    }
+    const int rc = prepare_group(groups[k], c, js.data(), es.data(), (int)js.size(), njobs, k == 0 ? s : s2, force);
+    if (rc) return rc;
   }
   int maxTot = 0;
   for (const PassGroup& g : groups) {
-    hipLaunchKernelGGL(k_zero_err, dim3(8, g.nb), dim3(256), 0, g.s, g.a);
+    launch_group_edges(g, c, false);
     maxTot = std::max(maxTot, g.maxTot);
   }
   for (int t = 0; t <= maxTot; ++t)
-    for (const PassGroup& g : groups)
+    for (PassGroup& g : groups)
       if (g.maxTot > 0 && t <= g.maxTot) launch_tick(g, c, t);
-  for (const PassGroup& g : groups) {
-    // (the split passes update the probe in place: nothing to copy back)
-    if (!g.split) hipLaunchKernelGGL(k_probe_back, dim3(64, g.nb), dim3(256), 0, g.s, g.a);
-    hipLaunchKernelGGL(k_finish, dim3(1, g.nb), dim3(256), 0, g.s, g.a, g.eo);
-  }
+  for (const PassGroup& g : groups) launch_group_edges(g, c, true);
   MRPIE_HIP(hipGetLastError());
   return MRPIE_OK;
 }

@@ -23,6 +23,7 @@ struct JobRec {
   char* ws;
   int* status;
   int H, W, N, M, J, T;
+  int t0 = 0;         // first tick of the job in its launch lane (batched calls)
 };
 
 struct LaunchArgs {

@@ -147,12 +147,14 @@ int mrpie_autotune(int32_t N, int32_t M, int32_t batch, int32_t J, int32_t reps,
     (void)hipEventDestroy(e0);
     return fail(MRPIE_EDEVICE, "hipEventCreate failed");
   }
-  float best_ms = 0.f;
-  int best_i = -1;
-  for (int i = 0; i < n && rc == MRPIE_OK; ++i) {
-    set_tuning(N, M, nb, cands[i]);
-    float t_best = 0.f;
-    for (int r = 0; r <= reps && rc == MRPIE_OK; ++r) {  // the first run warms up
+  // Round-robin over the candidates, `reps` timed rounds after one warm-up
+  // round, each candidate keeping its best time: a drift of the clocks
+  // during the run then shifts every candidate alike instead of favouring
+  // the ones timed while the GPU ran fastest.
+  std::vector<float> t_best((size_t)n, 0.f);
+  for (int r = 0; r <= reps && rc == MRPIE_OK; ++r) {
+    for (int i = 0; i < n && rc == MRPIE_OK; ++i) {
+      set_tuning(N, M, nb, cands[i]);
       hipError_t e = hipEventRecord(e0, s);
       if (e == hipSuccess) rc = run_sweep(c, jobs.data(), batch, nullptr, s);
       if (rc == MRPIE_OK && e == hipSuccess) e = hipEventRecord(e1, s);
@@ -160,12 +162,15 @@ int mrpie_autotune(int32_t N, int32_t M, int32_t batch, int32_t J, int32_t reps,
       float ms = 0.f;
       if (rc == MRPIE_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess && rc == MRPIE_OK) rc = hip_fail(e, "autotune timing");
-      if (r > 0 && (r == 1 || ms < t_best)) t_best = ms;
+      if (r > 0 && (r == 1 || ms < t_best[i])) t_best[i] = ms;
     }
-    if (rc != MRPIE_OK) break;
-    if (cand_ms) cand_ms[i] = t_best;
-    if (best_i < 0 || t_best < best_ms) {
-      best_ms = t_best;
+  }
+  float best_ms = 0.f;
+  int best_i = -1;
+  for (int i = 0; i < n && rc == MRPIE_OK; ++i) {
+    if (cand_ms) cand_ms[i] = t_best[i];
+    if (best_i < 0 || t_best[i] < best_ms) {
+      best_ms = t_best[i];
       best_i = i;
     }
   }

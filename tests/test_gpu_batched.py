@@ -55,10 +55,11 @@ def test_batched_equals_plain_per_job(inplace, width, split):
 
 def test_batched_more_jobs_than_one_launch():
     """More jobs than one launch's job table holds (36), on each of the two
-    streams: the driver splits each stream's share into launch groups.  80
-    equal jobs of 64^2 x 1 through the row / column passes (the default in
-    batches) give bitwise equal results whichever stream and group they land
-    in, and match the single-job sweep to float rounding; 40 through the
+    streams: the driver deals each stream's share to 36 launch lanes, and
+    the 4 jobs left over start when a lane frees up.  80 equal jobs of
+    64^2 x 1 through the row / column passes (the default in batches) give
+    bitwise equal results whichever stream, lane and start tick they get,
+    and match the single-job sweep to float rounding; 40 through the
     one-workgroup LDS sweep (forced by the tuning) equal the single-job LDS
     sweep bitwise."""
     from paper_2205_04295_amd import api
