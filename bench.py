@@ -343,21 +343,21 @@ def measure_adjoint(api, torch, dev, obj, probe, pos, I, args):
     # whole path: (6 + 3M) 2-D FFTs of N^2 per position (loss and adjoint,
     # exit waves recomputed), the FFT-dominated work of the gradient
     flops_pos = (6 + 3 * M) * fft2_flops(N)
-    ms, cnt, units = kt["k_adj_p4"]
-    p4_flops = 2 * M * fft2_flops(N) / 2  # 2M column halves of a 2-D FFT
+    ms, cnt, units = kt["k_adj_p3"]
+    p3_flops = 2 * M * fft2_flops(N) / 2  # 2M column halves of a 2-D FFT
     path_tf = flops_pos * J / el / 1e12
-    p4_tf = p4_flops * units / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    p3_tf = p3_flops * units / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"value": round(J / el, 1), "unit": "positions/s (loss + gradient)", "ms_per_eval": round(el * 1e3, 3),
             "loss": float(L.item()),
             "roofline": {"bound": "alu", "achieved": round(path_tf, 2), "peak": FP32_VALU_PEAK_TFS,
                          "unit": "TFLOP/s", "frac": round(path_tf / FP32_VALU_PEAK_TFS, 4),
                          "scope": "whole loss + gradient: (6 + 3M) N^2 2-D FFTs per position",
                          "flops_per_position": flops_pos},
-            "dominant_kernel": {"kernel": "k_adj_p4", "avg_us": round(ms * 1e3, 3), "launches_timed": int(cnt),
+            "dominant_kernel": {"kernel": "k_adj_p3", "avg_us": round(ms * 1e3, 3), "launches_timed": int(cnt),
                                 "positions_per_launch": round(units, 2),
-                                "achieved_TFs": round(p4_tf, 2),
-                                "frac": round(p4_tf / FP32_VALU_PEAK_TFS, 4),
-                                "flops_per_position": p4_flops}}
+                                "achieved_TFs": round(p3_tf, 2),
+                                "frac": round(p3_tf / FP32_VALU_PEAK_TFS, 4),
+                                "flops_per_position": p3_flops}}
 
 
 def measure_sparse(api, torch, dev, w, args):

@@ -350,7 +350,7 @@ int mrpie_canvas(const mrpie_problem* pb, const void* probe, const float* pos, f
  * = 0 switches timing off).  Classes: 0 = sweep row pass (k_rows, k_rows1),
  * 1 = sweep column pass (k_cols, k_cols1), 2 = registration column pass
  * (k_reg_cols), 3 = registration window GEMM (k_reg_gemm1), 4 = adjoint
- * modulus pass (k_adj_p4), 5 = one-workgroup LDS sweep (k_lds_sweep),
+ * modulus pass (k_adj_p3), 5 = one-workgroup LDS sweep (k_lds_sweep),
  * 6 = split update pass (k_upd), 7 = split gather pass (k_gat).
  * The events are created without the system-scope fence, which would
  * otherwise write the L2 back inside the timed dispatch.

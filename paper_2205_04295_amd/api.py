@@ -232,7 +232,7 @@ def validate(problem: Problem, **params) -> int:
     return lib.mrpie_validate(C.byref(problem), C.byref(prm))
 
 
-TIMED_KERNELS = ("k_rows", "k_cols", "k_reg_cols", "k_reg_gemm1", "k_adj_p4", "k_lds_sweep", "k_upd", "k_gat")
+TIMED_KERNELS = ("k_rows", "k_cols", "k_reg_cols", "k_reg_gemm1", "k_adj_p3", "k_lds_sweep", "k_upd", "k_gat")
 
 
 def timing_enable(stride: int):

@@ -31,35 +31,22 @@ constexpr int kAdjThreads = 256;
 
 __device__ __forceinline__ size_t chunk_off(int b, int N) { return (size_t)b * N * N; }
 
-// Single-field row passes take kAdjRows rows per workgroup, so that every
-// thread has a butterfly in most FFT stages (one 256-point row alone keeps
-// 32 of 256 threads busy in a radix-8 stage).
-constexpr int kAdjRows = 4;
-
-// P1 (rows): gather crop rows r0.. of position j0 + b, row FFTs -> Cp
-template <int N>
-__device__ void adj_p1(const AdjArgs& a, float2* smem) {
-  const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
-  const int j = a.j0 + b;
-  float2* tw = smem;
-  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
-  float2* A = tw + N;                // kAdjRows PT
-  float2* B = A + kAdjRows * PT;     // kAdjRows PT
-  const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
-  const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
-    const int rr = i / N, c = i - rr * N;
-    A[rr * PT + c] = a.obj[(size_t)(ny + r0 + rr) * a.W + nx + c];
-  }
-  load_twiddles<N, kAdjThreads>(tw);
-  __syncthreads();
-  float2* R = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, kAdjRows, tw);
-  float2* cp = a.Cp + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
-    const int rr = i / N, c = i - rr * N;
-    cp[i] = R[rr * PT + c];
-  }
-}
+// The 2-D transforms are split into row and column passes, and the Fourier
+// move is separable, S_f = S_y S_x: S_y moves along columns by fy
+// (e^{+2 pi i ky fy/N}), S_x along rows by fx.  Each 1-D move, each
+// component of the position gradient and each back-move then rides in a
+// pass over the axis it acts on:
+//   P1 (cols): crop columns -> C = S_y(crop)
+//   P2 (rows): o = S_x(C); exit waves P_p o, row FFTs
+//   P3 (cols): column FFTs; loss and modulus weight; inverse column FFTs
+//   P4 (rows): inverse row FFTs -> chi_p; probe-gradient terms; g;
+//              dL/df_x = Re <g, d_x o>; h = S_{-x}(g)
+//   P5 (cols): dL/df_y = Re <h, d_y C>; S_{-y}(h) = S_{-f}(g)
+// (<a, b> = sum conj(a) b, d_x and d_y the band-limited derivatives along x
+// and y; S_x is unitary and commutes with d_y, so Re <g, d_y o> =
+// Re <S_{-x} g, d_y S_y crop>.)  A 1-D term of the gradient is the
+// unnormalised-DFT Parseval sum (1/N) sum_k Re(conj(F a)(k) (2 pi i k/N)
+// (F b)(k)) over each row or column.
 
 __device__ __forceinline__ void frac_of(const AdjArgs& a, int j, int N, float* fy, float* fx) {
   *fy = 0.f;
@@ -87,27 +74,29 @@ __device__ __forceinline__ int col_group(int nunits) {
   return (nunits & 7) == 0 ? xcd_unit(blockIdx.x, nunits) : (int)blockIdx.x;
 }
 
-// P2 (cols): F(crop) -> F(o) = F(crop) e^{+2 pi i k.f/N}; stores F(o)
-// (unnormalised) and the inverse column pass of F(o)/N^2 into Cp
+
+// P1 (cols): crop columns u0.. of position j0 + b, gathered from the object;
+// C = S_y(crop) = F_y^-1(F_y(crop) e^{+2 pi i ky fy/N}) -> Cp
 template <int N>
-__device__ void adj_p2(const AdjArgs& a, float2* smem) {
+__device__ void adj_p1(const AdjArgs& a, float2* smem) {
   constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
   constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   const int u = col_group(gridDim.x), b = blockIdx.y;
   if (u >= N / CW) return;
   const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
+  const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
+  const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
   float fy, fx;
   frac_of(a, j, N, &fy, &fx);
   float2* tw = smem;
-  float2* A = tw + N;       // transform c at c * N
+  float2* A = tw + N;       // transform c at c * PT
   float2* B = A + CW * PT;
-  float2* cp = a.Cp + chunk_off(b, N);
   float2 v[PIX];
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    v[i] = cp[(size_t)k * N + u0 + c];
+    v[i] = a.obj[(size_t)(ny + k) * a.W + nx + u0 + c];
   }
   load_twiddles<N, kAdjThreads>(tw);
 #pragma unroll
@@ -119,17 +108,17 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
   __syncthreads();
   float2* F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, CW, tw);
   float2* G = (F == A) ? B : A;
+  const float invN = 1.f / (float)N;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
-    const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
-    const float2 fo = cmul(F[c * PT + k], ramp(ky, kx, fy, fx, 1.f, N));
-    a.Fo[chunk_off(b, N) + (size_t)k * N + uc] = fo;
-    G[c * PT + k] = cscale(fo, 1.f / ((float)N * (float)N));
+    const int ky = k < N / 2 ? k : k - N;
+    G[c * PT + k] = cscale(cmul(F[c * PT + k], ramp(ky, 0, fy, 0.f, 1.f, N)), invN);
   }
   __syncthreads();
   float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(G, F, CW, tw);
+  float2* cp = a.Cp + chunk_off(b, N);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -138,59 +127,91 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
   }
 }
 
-// P3 (rows): o row r; exit waves P_p o, row FFTs -> Psi
+// Row passes that hold one row of a position per thread take this many
+// positions per workgroup step, so that each FFT call keeps more of the
+// workgroup's threads busy (one 256-point row keeps 32 of 256 busy in a
+// radix-8 stage).
+constexpr int kAdjRowPos = 2;
+
+// P2 (rows): row r of C; o = S_x(C) (-> Ob); exit waves P_p o, row FFTs ->
+// Psi.  A workgroup takes row r of kAdjRowPos consecutive positions, so each
+// FFT call transforms that many rows (or M times as many) at once.
 template <int N>
-__device__ void adj_p3(const AdjArgs& a, float2* smem) {
+__device__ void adj_p2(const AdjArgs& a, float2* smem) {
   constexpr int MM = MRPIE_MAX_MODES;
-  const int r = blockIdx.x, b = blockIdx.y, M = a.M;
+  const int r = blockIdx.x, b0 = kAdjRowPos * blockIdx.y, M = a.M;
+  const int ns = min(kAdjRowPos, a.nb - b0);  // positions of this workgroup
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
   constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
-  float2* A = tw + N;            // (M+1) PT
-  float2* B = A + (M + 1) * PT;  // (M+1) PT
+  float2* A = tw + N;                    // kAdjRowPos M PT
+  float2* B = A + kAdjRowPos * M * PT;   // kAdjRowPos M PT
   const int c = threadIdx.x;
-  float2* cp = a.Cp + chunk_off(b, N);
-  float2 v = make_float2(0.f, 0.f), P[MM];
+  const int kx = c < N / 2 ? c : c - N;
+  float2 v[kAdjRowPos], P[MM];
+  float fx[kAdjRowPos] = {};
   if (c < N) {
-    v = cp[(size_t)r * N + c];
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (q < ns) v[q] = a.Cp[chunk_off(b0 + q, N) + (size_t)r * N + c];
 #pragma unroll
     for (int p = 0; p < MM; ++p)
       if (p < M) P[p] = a.probe[p * NN + (size_t)r * N + c];
   }
-  load_twiddles<N, kAdjThreads>(tw);
-  if (c < N) A[c] = v;
-  __syncthreads();
-  float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, 1, tw);
-  float2* W = (R == A) ? B : A;
-  if (c < N) {
-    const float2 o = R[c];
-    cp[(size_t)r * N + c] = o;  // Cp now holds o
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) W[p * PT + c] = cmul(P[p], o);
+  for (int q = 0; q < kAdjRowPos; ++q) {
+    float fy;
+    if (q < ns) frac_of(a, a.j0 + b0 + q, N, &fy, &fx[q]);
+  }
+  load_twiddles<N, kAdjThreads>(tw);
+  if (c < N) {
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (q < ns) A[q * PT + c] = v[q];
   }
   __syncthreads();
-  float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, M, tw);
-  float2* psi = a.Psi + (size_t)b * M * NN;
-  for (int i = threadIdx.x; i < M * N; i += kAdjThreads) {
-    const int p = i / N, cc = i - p * N;
-    psi[p * NN + (size_t)r * N + cc] = S[p * PT + cc];
+  float2* X = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, ns, tw);
+  float2* Y = (X == A) ? B : A;
+  if (c < N) {
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (q < ns) Y[q * PT + c] = cscale(cmul(X[q * PT + c], ramp(0, kx, 0.f, fx[q], 1.f, N)), 1.f / (float)N);
+  }
+  __syncthreads();
+  float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(Y, X, ns, tw);
+  float2* W = (R == A) ? B : A;
+  if (c < N) {
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (q < ns) {
+        const float2 o = R[q * PT + c];
+        a.Ob[chunk_off(b0 + q, N) + (size_t)r * N + c] = o;
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) W[(q * M + p) * PT + c] = cmul(P[p], o);
+      }
+  }
+  __syncthreads();
+  float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, ns * M, tw);
+  for (int i = threadIdx.x; i < ns * M * N; i += kAdjThreads) {
+    const int t = i / N, cc = i - t * N, q = t / M, p = t - q * M;
+    a.Psi[((size_t)(b0 + q) * M + p) * NN + (size_t)r * N + cc] = S[t * PT + cc];
   }
 }
 
-// P4 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
+// P3 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
 // IP: in-place transforms (one M CW N buffer instead of two, so more
 // workgroups share a CU; used while the register arrays it needs stay small)
-// The mode pass takes kAdjP4Group consecutive positions per workgroup (up to
+// The mode pass takes kAdjP3Group consecutive positions per workgroup (up to
 // four modes; one with more, where the prefetch registers would spill) and
 // loads the next position's spectra and pattern columns while the current
 // one's transforms run.
-constexpr int kAdjP4Group = 4;
-__host__ __device__ constexpr int adj_p4_group(int mm) { return mm <= 4 ? kAdjP4Group : 1; }
+constexpr int kAdjP3Group = 4;
+__host__ __device__ constexpr int adj_p3_group(int mm) { return mm <= 4 ? kAdjP3Group : 1; }
 
 template <int N, int MM, bool IP>
-__device__ void adj_p4(const AdjArgs& a, float2* smem) {
-  constexpr int CW = kAdjCWM, PIX = (N * CW + 255) / 256, GRP = adj_p4_group(MM);
+__device__ void adj_p3(const AdjArgs& a, float2* smem) {
+  constexpr int CW = kAdjCWM, PIX = (N * CW + 255) / 256, GRP = adj_p3_group(MM);
   const int u = col_group(gridDim.x), M = a.M;
   if (u >= N / CW) return;
   const int b0 = blockIdx.y * GRP, b1 = min(b0 + GRP, a.nb);
@@ -288,24 +309,28 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
   }
 }
 
-// P5 (rows): chi row r; g = 2 sum_p conj(P_p) chi_p, row FFT.  A workgroup
-// takes row r of kAdjGroup consecutive positions in order and sums their
-// probe-gradient terms 2 conj(o) chi_p in registers; the group's partial
-// replaces row r of its first position's Psi (which only this workgroup
-// reads), so the probe gradient is reduced from one array per group.
+// P4 (rows): chi row r; g = 2 sum_p conj(P_p) chi_p; the x part of the
+// position gradient from F_x g and F_x o; h = S_{-x}(g) -> G.  A workgroup
+// takes row r of kAdjGroup consecutive positions, kAdjRowPos at a time (each
+// FFT call transforms all of their rows), and sums their probe-gradient terms
+// 2 conj(o) chi_p in registers; the group's partial replaces row r of its
+// first position's Psi (which only this workgroup reads), so the probe
+// gradient is reduced from one array per group.  Each wave stores its own
+// partial of the x gradient (no workgroup barrier per position).
 constexpr int kAdjGroup = 8;
 
-template <int N>
-__device__ void adj_p5(const AdjArgs& a, float2* smem) {
-  constexpr int MM = MRPIE_MAX_MODES;
+template <int N, int MM>
+__device__ void adj_p4(const AdjArgs& a, float2* smem) {
   const int r = blockIdx.x, M = a.M;
+  const int NB = M > 2 ? kAdjRowPos * M : 2 * kAdjRowPos;  // transforms per buffer: the step's modes, then its g and o
   const int b0 = blockIdx.y * kAdjGroup, b1 = min(b0 + kAdjGroup, a.nb);
   const size_t NN = (size_t)N * N;
   float2* tw = smem;
   constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
-  float2* A = tw + N;       // M PT
-  float2* B = A + M * PT;   // M PT
-  const int c = threadIdx.x;
+  float2* A = tw + N;        // NB PT
+  float2* B = A + NB * PT;   // NB PT
+  const int c = threadIdx.x, wave = threadIdx.x >> 6;
+  const int kx = c < N / 2 ? c : c - N;
   const size_t roff = (size_t)r * N + c;
   float2 P[MM], acc[MM];
 #pragma unroll
@@ -314,50 +339,91 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
     if (p < M && c < N) P[p] = a.probe[p * NN + roff];
   }
   load_twiddles<N, kAdjThreads>(tw);
-  // software pipeline: the next position's spectra row and patch row are
-  // loaded into registers while this position's transforms run (the LDS
-  // barriers of the transforms leave those loads in flight)
-  float2 nv[MM], no = make_float2(0.f, 0.f);
-  if (c < N && b0 < b1) {
-    const float2* psi0 = a.Psi + (size_t)b0 * M * NN;
-    no = a.Cp[chunk_off(b0, N) + roff];
+  // software pipeline: the next step's spectra rows and o rows are loaded
+  // into registers while this step's transforms run (the LDS barriers of
+  // the transforms leave those loads in flight)
+  float2 nv[kAdjRowPos][MM], no[kAdjRowPos];
+  auto fetch = [&](int bb) {
+    if (c >= N) return;
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) nv[p] = psi0[p * NN + roff];
-  }
-  for (int b = b0; b < b1; ++b) {
-    float2 o = make_float2(0.f, 0.f);
-    if (c < N) {
-      o = no;
-#pragma unroll
-      for (int p = 0; p < MM; ++p)
-        if (p < M) A[p * PT + c] = nv[p];
-      if (b + 1 < b1) {
-        const float2* psin = a.Psi + (size_t)(b + 1) * M * NN;
-        no = a.Cp[chunk_off(b + 1, N) + roff];
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (bb + q < b1) {
+        no[q] = a.Ob[chunk_off(bb + q, N) + roff];
 #pragma unroll
         for (int p = 0; p < MM; ++p)
-          if (p < M) nv[p] = psin[p * NN + roff];
+          if (p < M) nv[q][p] = a.Psi[((size_t)(bb + q) * M + p) * NN + roff];
       }
+  };
+  if (b0 < b1) fetch(b0);
+  for (int b = b0; b < b1; b += kAdjRowPos) {
+    const int ns = min(kAdjRowPos, b1 - b);
+    float fx[kAdjRowPos] = {};
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q) {
+      float fy;
+      if (q < ns) frac_of(a, a.j0 + b + q, N, &fy, &fx[q]);
     }
+    float2 o[kAdjRowPos];
+    if (c < N) {
+#pragma unroll
+      for (int q = 0; q < kAdjRowPos; ++q)
+        if (q < ns) {
+          o[q] = no[q];
+#pragma unroll
+          for (int p = 0; p < MM; ++p)
+            if (p < M) A[(q * M + p) * PT + c] = nv[q][p];
+        }
+    }
+    if (b + kAdjRowPos < b1) fetch(b + kAdjRowPos);
     lds_barrier();
-    float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, M, tw);
+    float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, ns * M, tw);
     float2* W = (R == A) ? B : A;
     if (c < N) {
-      float2 g = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int p = 0; p < MM; ++p)
-        if (p < M) {
-          const float2 chi = R[p * PT + c];
-          acc[p] = cadd(acc[p], cscale(cmulc(chi, o), 2.f));   // 2 chi conj(o)
-          g = cadd(g, cmulc(chi, P[p]));
+      for (int q = 0; q < kAdjRowPos; ++q)
+        if (q < ns) {
+          float2 g = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int p = 0; p < MM; ++p)
+            if (p < M) {
+              const float2 chi = R[(q * M + p) * PT + c];
+              acc[p] = cadd(acc[p], cscale(cmulc(chi, o[q]), 2.f));   // 2 chi conj(o)
+              g = cadd(g, cmulc(chi, P[p]));
+            }
+          W[(2 * q) * PT + c] = cscale(g, 2.f);
+          W[(2 * q + 1) * PT + c] = o[q];
         }
-      W[c] = cscale(g, 2.f);
     }
     lds_barrier();
-    float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, 1, tw);
-    if (c < N) a.G[chunk_off(b, N) + roff] = S[c];
-    lds_barrier();  // A, B are reused by the next position
+    float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, 2 * ns, tw);  // F_x g, F_x o
+    float2* T = (S == A) ? B : A;
+    double gx[kAdjRowPos] = {};
+    if (c < N) {
+#pragma unroll
+      for (int q = 0; q < kAdjRowPos; ++q)
+        if (q < ns) {
+          const float2 fg = S[(2 * q) * PT + c];
+          // Re conj(F g) (i w) F o = -w Im(conj(F g) F o), w = 2 pi kx / N
+          const float2 cf = cmulc(S[(2 * q + 1) * PT + c], fg);  // F o conj(F g)
+          gx[q] = -2.0 * M_PI * (double)kx / (double)N * (double)cf.y / (double)N;
+          T[q * PT + c] = cscale(cmul(fg, ramp(0, kx, 0.f, fx[q], -1.f, N)), 1.f / (float)N);
+        }
+    }
+    lds_barrier();
+    float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(T, S, ns, tw);
+    if (c < N) {
+#pragma unroll
+      for (int q = 0; q < kAdjRowPos; ++q)
+        if (q < ns) a.G[chunk_off(b + q, N) + roff] = H[q * PT + c];
+    }
+#pragma unroll
+    for (int q = 0; q < kAdjRowPos; ++q)
+      if (q < ns) {
+        const double v = wave_sum(gx[q]);
+        if ((threadIdx.x & 63) == 0 && a.subpixel)
+          a.pos_part[((size_t)(b + q) * N + r) * kPosSlots + 1 + wave] = v;
+      }
+    lds_barrier();  // A, B are reused by the next step
   }
   if (c < N) {
     float2* part = a.Psi + (size_t)b0 * M * NN;
@@ -367,9 +433,10 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
   }
 }
 
-// P6 (cols): F(g); position-gradient partials; S_{-f}: x e^{-2 pi i k.f/N}/N^2
+// P5 (cols): the y part of the position gradient from F_y h and F_y C;
+// S_{-y}(h) = S_{-f}(g) -> G (the object-gradient term)
 template <int N>
-__device__ void adj_p6(const AdjArgs& a, float2* smem) {
+__device__ void adj_p5(const AdjArgs& a, float2* smem) {
   constexpr int CW = kAdjCW1, PIX = (N * CW + 255) / 256;
   constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   const int u = col_group(gridDim.x), b = blockIdx.y;
@@ -382,41 +449,48 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
   float2* B = A + CW * PT;
   __shared__ double redd[16];
   float2* g = a.G + chunk_off(b, N);
-  const float2* Fo = a.Fo + chunk_off(b, N);
-  float2 v[PIX];
+  const float2* cp = a.Cp + chunk_off(b, N);
+  float2 hv[PIX], cv[PIX];
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    v[i] = g[(size_t)k * N + u0 + c];
+    cv[i] = cp[(size_t)k * N + u0 + c];
+    hv[i] = g[(size_t)k * N + u0 + c];
   }
   load_twiddles<N, kAdjThreads>(tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    A[c * PT + k] = v[i];
+    A[c * PT + k] = cv[i];
   }
   __syncthreads();
-  float2* F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, CW, tw);
-  float2* G2 = (F == A) ? B : A;
-  double gy = 0.0, gx = 0.0;
+  float2* F = fft_lds<N, false, false, kAdjThreads, PT, true>(A, B, CW, tw);  // F_y C
+  float2* X = (F == A) ? B : A;
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
-    const int q = tid + 256 * i, k = q / CW, c = q - k * CW, uc = u0 + c;
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
     if (q >= N * CW) continue;
-    const int ky = k < N / 2 ? k : k - N, kx = uc < N / 2 ? uc : uc - N;
-    const float2 fg = F[c * PT + k];
-    // Re conj(Fg) (i w) Fo = -w Im(conj(Fg) Fo), w = 2 pi k / N; unitary
-    // spectra are the unnormalised ones / N
-    const float2 cf = cmulc(Fo[(size_t)k * N + uc], fg);  // Fo conj(Fg)
-    const double im = (double)cf.y / ((double)N * (double)N);
-    gy += -2.0 * M_PI * (double)ky / (double)N * im;
-    gx += -2.0 * M_PI * (double)kx / (double)N * im;
-    G2[c * PT + k] = cscale(cmul(fg, ramp(ky, kx, fy, fx, -1.f, N)), 1.f / ((float)N * (float)N));
+    cv[i] = F[c * PT + k];
+    X[c * PT + k] = hv[i];
   }
   __syncthreads();
-  float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(G2, F, CW, tw);
+  float2* Fh = fft_lds<N, false, false, kAdjThreads, PT, true>(X, F, CW, tw);  // F_y h
+  float2* Y = (Fh == A) ? B : A;
+  double gy = 0.0;
+#pragma unroll
+  for (int i = 0; i < PIX; ++i) {
+    const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
+    if (q >= N * CW) continue;
+    const int ky = k < N / 2 ? k : k - N;
+    const float2 fh = Fh[c * PT + k];
+    const float2 cf = cmulc(cv[i], fh);  // F C conj(F h)
+    gy += -2.0 * M_PI * (double)ky / (double)N * (double)cf.y / (double)N;
+    Y[c * PT + k] = cscale(cmul(fh, ramp(ky, 0, fy, 0.f, -1.f, N)), 1.f / (float)N);
+  }
+  __syncthreads();
+  float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(Y, Fh, CW, tw);
 #pragma unroll
   for (int i = 0; i < PIX; ++i) {
     const int q = tid + 256 * i, k = q / CW, c = q - k * CW;
@@ -424,34 +498,8 @@ __device__ void adj_p6(const AdjArgs& a, float2* smem) {
     g[(size_t)k * N + u0 + c] = H[c * PT + k];
   }
   gy = block_sum(gy, redd);
-  gx = block_sum(gx, redd);
   // one partial per column group, in the slot of its first column
-  if (tid < CW && a.subpixel) {
-    a.pos_part[((size_t)b * N + u0 + tid) * 2] = tid == 0 ? gy : 0.0;
-    a.pos_part[((size_t)b * N + u0 + tid) * 2 + 1] = tid == 0 ? gx : 0.0;
-  }
-}
-
-// P7 (rows): inverse row FFTs -> S_{-f}(g) rows r0.. (object-gradient term)
-template <int N>
-__device__ void adj_p7(const AdjArgs& a, float2* smem) {
-  const int r0 = blockIdx.x * kAdjRows, b = blockIdx.y;
-  float2* tw = smem;
-  constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch (padded intermediates)
-  float2* A = tw + N;                // kAdjRows PT
-  float2* B = A + kAdjRows * PT;     // kAdjRows PT
-  float2* g = a.G + chunk_off(b, N) + (size_t)r0 * N;
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
-    const int rr = i / N, c = i - rr * N;
-    A[rr * PT + c] = g[i];
-  }
-  load_twiddles<N, kAdjThreads>(tw);
-  __syncthreads();
-  float2* R = fft_lds<N, true, false, kAdjThreads, PT, true>(A, B, kAdjRows, tw);
-  for (int i = threadIdx.x; i < kAdjRows * N; i += kAdjThreads) {
-    const int rr = i / N, c = i - rr * N;
-    g[i] = R[rr * PT + c];
-  }
+  if (tid < CW && a.subpixel) a.pos_part[((size_t)b * N + u0 + tid) * kPosSlots] = tid == 0 ? gy : 0.0;
 }
 
 #define MRPIE_ADJ_KERNEL(NAME, FN)                       \
@@ -467,24 +515,32 @@ __device__ void adj_p7(const AdjArgs& a, float2* smem) {
   }
 MRPIE_ADJ_KERNEL(k_adj_p1, adj_p1)
 MRPIE_ADJ_KERNEL(k_adj_p2, adj_p2)
-MRPIE_ADJ_KERNEL(k_adj_p3, adj_p3)
 // the mode pass per bound MM >= M on the modes (register arrays of the
 // in-place transforms)
 template <int MM>
-__global__ __launch_bounds__(256) void k_adj_p4(const AdjArgs a) {
+__global__ __launch_bounds__(256) void k_adj_p3(const AdjArgs a) {
   constexpr bool IP = MM <= 4;
   extern __shared__ float2 smem[];
   switch (a.N) {
-    case 32: adj_p4<32, MM, IP>(a, smem); break;
-    case 64: adj_p4<64, MM, IP>(a, smem); break;
-    case 128: adj_p4<128, MM, IP>(a, smem); break;
-    case 192: adj_p4<192, MM, IP>(a, smem); break;
-    default: adj_p4<256, MM, IP>(a, smem); break;
+    case 32: adj_p3<32, MM, IP>(a, smem); break;
+    case 64: adj_p3<64, MM, IP>(a, smem); break;
+    case 128: adj_p3<128, MM, IP>(a, smem); break;
+    case 192: adj_p3<192, MM, IP>(a, smem); break;
+    default: adj_p3<256, MM, IP>(a, smem); break;
+  }
+}
+template <int MM>
+__global__ __launch_bounds__(256) void k_adj_p4(const AdjArgs a) {
+  extern __shared__ float2 smem[];
+  switch (a.N) {
+    case 32: adj_p4<32, MM>(a, smem); break;
+    case 64: adj_p4<64, MM>(a, smem); break;
+    case 128: adj_p4<128, MM>(a, smem); break;
+    case 192: adj_p4<192, MM>(a, smem); break;
+    default: adj_p4<256, MM>(a, smem); break;
   }
 }
 MRPIE_ADJ_KERNEL(k_adj_p5, adj_p5)
-MRPIE_ADJ_KERNEL(k_adj_p6, adj_p6)
-MRPIE_ADJ_KERNEL(k_adj_p7, adj_p7)
 
 // ---------------------------------------------------------------- reductions
 // loss += sum over the chunk's (position, column) partials, in order: each
@@ -514,8 +570,9 @@ __global__ __launch_bounds__(256) void k_adj_pos(const AdjArgs a, int nb) {
   const int b = blockIdx.x;
   double gy = 0.0, gx = 0.0;
   for (int u = threadIdx.x; u < a.N; u += blockDim.x) {
-    gy += a.pos_part[((size_t)b * a.N + u) * 2];
-    gx += a.pos_part[((size_t)b * a.N + u) * 2 + 1];
+    const double* pp = a.pos_part + ((size_t)b * a.N + u) * kPosSlots;
+    gy += pp[0];
+    gx += (pp[1] + pp[2]) + (pp[3] + pp[4]);
   }
   gy = block_sum(gy, red);
   gx = block_sum(gx, red);
@@ -594,11 +651,11 @@ AdjLayout adj_layout(int N, int M, int J) {
   auto take = [&](size_t bytes) { size_t o = off; off = ws_align(off + bytes); return o; };
   L.chunk = B;
   L.Cp = take((size_t)B * NN * 8);
-  L.Fo = take((size_t)B * NN * 8);
+  L.Ob = take((size_t)B * NN * 8);
   L.G = take((size_t)B * NN * 8);
   L.Psi = take((size_t)B * M * NN * 8);
   L.loss_part = take((size_t)B * N * 8);
-  L.pos_part = take((size_t)B * N * 16);
+  L.pos_part = take((size_t)B * N * kPosSlots * 8);
   L.loss_blk = take((size_t)kLossBlocks * 8);
   L.loss_acc = take(16);
   L.total = off;
@@ -618,7 +675,7 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   AdjArgs a{};
   a.H = pb->H; a.W = pb->W; a.N = N; a.M = M; a.J = J; a.subpixel = subpixel;
   a.obj = obj; a.probe = probe; a.pos = pos; a.I = intens; a.status = status;
-  a.Cp = (float2*)(w + L.Cp); a.Fo = (float2*)(w + L.Fo); a.G = (float2*)(w + L.G); a.Psi = (float2*)(w + L.Psi);
+  a.Cp = (float2*)(w + L.Cp); a.Ob = (float2*)(w + L.Ob); a.G = (float2*)(w + L.G); a.Psi = (float2*)(w + L.Psi);
   a.loss_part = (double*)(w + L.loss_part); a.pos_part = (double*)(w + L.pos_part);
   a.loss_blk = (double*)(w + L.loss_blk);
   a.loss_acc = (double*)(w + L.loss_acc);
@@ -628,36 +685,35 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     hipLaunchKernelGGL(k_adj_zero, dim3(2048), dim3(256), 0, s, gobj, (size_t)pb->H * pb->W, (double*)nullptr);
     hipLaunchKernelGGL(k_adj_zero, dim3(256), dim3(256), 0, s, gprobe, (size_t)M * N * N, (double*)nullptr);
   }
-  // LDS of the row passes (one / M+1 / M transforms), of the single-field
-  // column passes (kAdjCW1 transforms) and of the mode column pass
-  // row passes: transforms at the padded pitch col_pitch<N, 1, true>()
+  // LDS of the row passes (kAdjRowPos M transforms; P4 at least 2 kAdjRowPos)
+  // at the padded pitch
+  // col_pitch<N, 1, true>(), of the single-field column passes (kAdjCW1
+  // transforms) and of the mode column pass at col_pitch<N, CW, true>()
   const size_t pr = (size_t)(N + N / 16 + 15) / 16 * 16;
-  const size_t l1 = (N + 2 * kAdjRows * pr) * 8, lm1 = (N + 2 * (M + 1) * pr) * 8, lm = (N + 2 * M * pr) * 8;
-  // (column passes: transforms at the pitch col_pitch<N, CW, true>())
-  const size_t pbase = (size_t)(N + N / 16 + 15) / 16 * 16, p1 = pbase + 16 / kAdjCW1, pm = pbase + 16 / kAdjCWM;
+  const size_t l2 = (N + 2 * kAdjRowPos * M * pr) * 8, l4 = (N + 2 * kAdjRowPos * std::max(M, 2) * pr) * 8;
+  const size_t pbase = pr, p1 = pbase + 16 / kAdjCW1, pm = pbase + 16 / kAdjCWM;
   const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * p1) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * pm) * 8;
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p3, lm1));
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lm));
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p2, lc1));
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p6, lc1));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p1, lc1));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p2, l2));
   const auto kp4 = M <= 1 ? k_adj_p4<1> : M <= 2 ? k_adj_p4<2> : M <= 4 ? k_adj_p4<4> : k_adj_p4<MRPIE_MAX_MODES>;
-  const int g4 = adj_p4_group(M <= 4 ? 4 : MRPIE_MAX_MODES);  // positions per workgroup of k_adj_p4
-  MRPIE_HIP(ensure_lds((const void*)kp4, lcm));
+  MRPIE_HIP(ensure_lds((const void*)kp4, l4));
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p5, lc1));
+  const auto kp3 = M <= 1 ? k_adj_p3<1> : M <= 2 ? k_adj_p3<2> : M <= 4 ? k_adj_p3<4> : k_adj_p3<MRPIE_MAX_MODES>;
+  const int g3 = adj_p3_group(M <= 4 ? 4 : MRPIE_MAX_MODES);  // positions per workgroup of k_adj_p3
+  MRPIE_HIP(ensure_lds((const void*)kp3, lcm));
   for (int j0 = 0; j0 < J; j0 += L.chunk) {
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     a.nb = nb;
-    const dim3 g(N, nb), gr(N / kAdjRows, nb), g1(N / kAdjCW1, nb), blk(kAdjThreads);
-    hipLaunchKernelGGL(k_adj_p1, gr, blk, l1, s, a);
-    hipLaunchKernelGGL(k_adj_p2, g1, blk, lc1, s, a);
-    hipLaunchKernelGGL(k_adj_p3, g, blk, lm1, s, a);
-    launch_ku(TK_ADJ, nb, kp4, dim3(N / kAdjCWM, (nb + g4 - 1) / g4), blk, lcm, s, a);  // timed per position
+    const dim3 g1(N / kAdjCW1, nb), blk(kAdjThreads);
+    hipLaunchKernelGGL(k_adj_p1, g1, blk, lc1, s, a);
+    hipLaunchKernelGGL(k_adj_p2, dim3(N, (nb + kAdjRowPos - 1) / kAdjRowPos), blk, l2, s, a);
+    launch_ku(TK_ADJ, nb, kp3, dim3(N / kAdjCWM, (nb + g3 - 1) / g3), blk, lcm, s, a);  // timed per position
     hipLaunchKernelGGL(k_adj_loss_part, dim3(kLossBlocks), blk, 0, s, a, nb);
     hipLaunchKernelGGL(k_adj_loss, dim3(1), dim3(kLossBlocks), 0, s, a);
     if (grads) {
-      hipLaunchKernelGGL(k_adj_p5, dim3(N, (nb + kAdjGroup - 1) / kAdjGroup), blk, lm, s, a);
-      hipLaunchKernelGGL(k_adj_p6, g1, blk, lc1, s, a);
-      hipLaunchKernelGGL(k_adj_p7, gr, blk, l1, s, a);
+      hipLaunchKernelGGL(kp4, dim3(N, (nb + kAdjGroup - 1) / kAdjGroup), blk, l4, s, a);
+      hipLaunchKernelGGL(k_adj_p5, g1, blk, lc1, s, a);
       hipLaunchKernelGGL(k_adj_pos, dim3(nb), blk, 0, s, a, nb);
       hipLaunchKernelGGL(k_adj_probe, dim3(512), blk, 0, s, a, nb);
       hipLaunchKernelGGL(k_adj_object, dim3((pb->W + kObjTile - 1) / kObjTile, (pb->H + kObjTile - 1) / kObjTile),
