@@ -38,20 +38,20 @@ FP32_VALU_PEAK_TFS = 78.6
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "da9e99e75e6d5cf393872ab16e2cfcb9d9e6244c170b80747b3b7957e6b848d8",
+    "sha256": "3f46fb866285786b5e1b4696d4cd0380ce9808dfbfabdd196d84f3da7fb902fa",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    ("k_rows", 1): {"fetch_kib": 3459.5, "write_kib": 4097.6},
-    ("k_cols", 1): {"fetch_kib": 997.5, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13531.8, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3723.5, "write_kib": 6160.0},
-    ("k_rows", 8): {"fetch_kib": 27341.0, "write_kib": 32780.7},
-    ("k_cols", 8): {"fetch_kib": 7318.0, "write_kib": 12320.0},
-    ("k_upd", 16): {"fetch_kib": 29138.7, "write_kib": 32865.3},
-    ("k_gat", 16): {"fetch_kib": 16727.0, "write_kib": 24832.1},
-    ("k_cols", 16): {"fetch_kib": 14539.0, "write_kib": 24640.0},
-    ("k_upd", 32): {"fetch_kib": 58196.0, "write_kib": 65730.6},
-    ("k_gat", 32): {"fetch_kib": 33369.3, "write_kib": 49664.5},
-    ("k_cols", 32): {"fetch_kib": 28916.4, "write_kib": 49434.8},
+    ("k_rows", 1): {"fetch_kib": 3457.5, "write_kib": 4097.6},
+    ("k_cols", 1): {"fetch_kib": 998.0, "write_kib": 1552.0},
+    ("k_rows", 4): {"fetch_kib": 13004.9, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3730.6, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 26200.7, "write_kib": 32780.7},
+    ("k_cols", 8): {"fetch_kib": 7325.0, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29144.2, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16721.5, "write_kib": 24832.1},
+    ("k_cols", 16): {"fetch_kib": 14547.5, "write_kib": 24640.0},
+    ("k_upd", 32): {"fetch_kib": 58203.1, "write_kib": 65730.6},
+    ("k_gat", 32): {"fetch_kib": 33364.2, "write_kib": 49664.6},
+    ("k_cols", 32): {"fetch_kib": 28926.1, "write_kib": 49447.8},
 }
 
 
