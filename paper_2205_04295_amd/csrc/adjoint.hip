@@ -69,6 +69,7 @@ __device__ __forceinline__ float2 ramp(int ky, int kx, float fy, float fx, float
 // k = q / CW, column c = q % CW (consecutive threads: consecutive columns).
 constexpr int kAdjCW1 = 8;  // passes with one transform per column
 constexpr int kAdjCWM = 4;  // the mode pass (M transforms per column)
+static_assert(kAdjCWM * 64 == kAdjThreads, "the mode pass stores one loss partial per wave and column");
 
 __device__ __forceinline__ int col_group(int nunits) {
   return (nunits & 7) == 0 ? xcd_unit(blockIdx.x, nunits) : (int)blockIdx.x;
@@ -221,7 +222,6 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
   constexpr int PT = col_pitch<N, CW, true>();  // LDS pitch (padded intermediates)
   float2* A = tw + N;          // transform (p, c) at (p * CW + c) * PT
   float2* B = IP ? A : A + M * CW * PT;
-  __shared__ double redd[16];
   // pixel q = tid + 256 i of the group: row k = q / CW, column c = q % CW
   float2 nv[PIX][MM];
   float nI[PIX];
@@ -303,9 +303,11 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
       for (int p = 0; p < MM; ++p)
         if (p < M) psi[p * NN + off] = H[(p * CW + c) * PT + k];
     }
-    e = block_sum(e, redd);  // (its barriers also end this position's reads of the LDS buffers)
-    // one partial per column group, in the slot of its first column
-    if (tid < CW) a.loss_part[(size_t)bb * N + u0 + tid] = tid == 0 ? e : 0.0;
+    // one partial per wave, in the slots of the group's CW columns (no
+    // workgroup reduction per position)
+    e = wave_sum(e);
+    if ((tid & 63) == 0) a.loss_part[(size_t)bb * N + u0 + (tid >> 6)] = e;
+    lds_barrier();  // this position's reads of the LDS buffers end before the next one's writes
   }
 }
 

@@ -21,7 +21,8 @@ struct AdjArgs {
   float2* Psi;         // [chunk][M][N][N] row spectra of the exit waves -> row
                        // spectra of chi; slot of each group's first position
                        // -> the group's probe-gradient partial
-  double* loss_part;   // [chunk][N]
+  double* loss_part;   // [chunk][N]: the mode pass's partial of each wave, in the
+                       // slot of its column group's column of the same index
   double* pos_part;    // [chunk][N][kPosSlots]: [b][u][0] y part per column
                        // group (first column's slot), [b][r][1 + w] x part
                        // of row r from wave w
