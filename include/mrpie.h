@@ -234,7 +234,13 @@ int mrpie_get_tuning(int32_t N, int32_t M, int32_t batched, mrpie_tuning* t);
  * refine, subpixel and propagator must be 0, else MRPIE_EUNSUPPORTED) on
  * `njobs` independent reconstructions of any mix of N, M, J and object
  * size, lock-step by position: every launch advances one position of every
- * unfinished job, so one pair of launches carries the work of all jobs.
+ * running job, so one pair of launches carries the work of many jobs.  The
+ * jobs of a stream run in at most 36 launch lanes (the job table of one
+ * launch); a share of more than 36 jobs is dealt to the lanes longest job
+ * first, and a job starts once the job ahead of it in its lane has taken
+ * its last step.  Jobs run concurrently, so they must not share object,
+ * probe, workspace or error-curve memory (positions and intensities are
+ * only read and may be shared; so may status words).
  * Each job's object and probe match those of a mrpie_rpie call on that job
  * alone to float rounding (the single-job column pass keeps its first and
  * last FFT stages in registers; jobs that run the one-workgroup LDS sweep in
