@@ -33,12 +33,13 @@ FP32_VALU_PEAK_TFS = 78.6
 # (profiles/sweep_spiral256x3_trace_counters.md).  Keyed by (timed kernel
 # class, jobs per launch): 1 = the single-job kernels k_rows1 / k_cols1;
 # k_upd / k_gat are the split row passes of batches of 16 or more jobs.
-# Valid only for the kernel sources they were taken on: bench reports
-# traffic = null when the sources differ or the launch shape was not measured.
+# Valid only for the kernel sources they were taken on (hashed with their
+# comments removed): bench reports traffic = null when the code differs or
+# the launch shape was not measured.
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "3f46fb866285786b5e1b4696d4cd0380ce9808dfbfabdd196d84f3da7fb902fa",
+    "sha256": "872b0f15a31d7e1f5aa4925e4a0be7a124e626f0e9be50fd33b0bb016c4595f6",
     "fetch_factor": 2.000, "write_factor": 1.000,
     ("k_rows", 1): {"fetch_kib": 3457.5, "write_kib": 4097.6},
     ("k_cols", 1): {"fetch_kib": 998.0, "write_kib": 1552.0},
@@ -56,11 +57,17 @@ COUNTERS = {
 
 
 def kernel_sources_sha256():
+    """SHA-256 of the sweep's kernel sources with comments, trailing blanks
+    and empty lines removed (an edit of a comment keeps the counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in COUNTERS["sources"]:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            code = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", "", code)
+        lines = [ln.rstrip() for ln in code.splitlines() if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()
 
 

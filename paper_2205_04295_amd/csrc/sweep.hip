@@ -27,6 +27,8 @@
 // Batching: blockIdx.y selects a job from the launch's job table; every job
 // advances one position per tick (lock-step), so many independent
 // reconstructions of different N, M, J fill the GPU that one sweep cannot.
+// A job table holds at most 36 jobs: more jobs queue in launch lanes, each
+// starting at a later tick (its own step is the tick minus its start).
 // Batches of 16 or more jobs (by default) split the row work into two
 // launches, k_upd (the update of step s-1) and k_gat (the gather of step
 // s), which read every row of the spectra once and keep no patch copy (see
