@@ -700,6 +700,180 @@ __device__ __forceinline__ void cols_body_rd(const JobRec& jb, int t, float2* sm
   }
 }
 
+// The register-direct column pass for CW > 1 adjacent columns per workgroup
+// (radix-8 three-stage plans): the same stage layout as cols_body_rd with
+// CW M transforms, transform (p, c) at (p CW + c) PT; IP: one buffer, each
+// LDS stage reading all of its inputs before any thread writes (one more
+// barrier per stage, half the LDS).
+// Consecutive threads take consecutive columns, so every global access
+// moves CW * 8 contiguous bytes of a row; the pitch N + 16 / CW puts the CW
+// transforms of one row index in different LDS banks.
+template <int N, int MM, int CW, bool IP>
+__device__ __forceinline__ void cols_body_rdw(const JobRec& jb, int t, float2* smem) {
+  using P = Plan8<N>;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2];
+  static_assert(R2 > 1 && P::R[3] == 1, "three-stage plans only");
+  constexpr int RL = R2;                         // last forward radix = first inverse radix
+  constexpr int Q0 = N / R0;                     // butterflies per transform of the first stage
+  constexpr int QL = N / RL;                     // mode-sum threads per column
+  constexpr int NT = 256;
+  constexpr int IT1 = (MM * CW * Q0 + NT - 1) / NT;  // first-stage butterflies per thread
+  static_assert(CW * QL <= NT, "one mode-sum thread per (column, frequency group)");
+  constexpr int PT = col_pitch<N, CW>();         // LDS pitch of a transform
+  const int M = jb.M;
+  const int total = jb.J * jb.T;
+  if (t < 0 || t >= total) return;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);  // column group of this workgroup
+  if (u >= N / CW) return;
+  const int u0 = u * CW;
+  const int it = t / jb.J, jn = t - it * jb.J;
+  const WsLayout L = ws_layout(N, M, jb.T);
+  const size_t NN = (size_t)N * N;
+  float2* psi = (float2*)(jb.ws + pick(L.psi, t & 1));
+  const float* Ij = jb.I + (size_t)jn * NN;
+  const int tid = threadIdx.x;
+
+  float2* tw = smem;
+  float2* bufA = tw + N;                    // M CW PT
+  float2* bufB = IP ? bufA : bufA + M * CW * PT;  // M CW PT
+
+  const size_t slot = (size_t)it * kErrSlots + u * (NT / 64) + (tid >> 6);
+  double* err_slot = (double*)(jb.ws + L.err) + slot;
+  double* isum_slot = (double*)(jb.ws + L.isum) + slot;
+  const double err_old = (tid & 63) == 0 ? *err_slot : 0.0;
+  const double isum_old = (tid & 63) == 0 ? *isum_slot : 0.0;
+
+  // first-stage inputs: butterfly b = tid + NT i is column c = b % CW,
+  // index j = (b / CW) % Q0 of transform (p, c), p = b / (CW Q0): rows
+  // j + Q0 r; and the patterns of the mode-sum threads
+  const int nb1 = M * CW * Q0;
+  float2 v[IT1][R0];
+#pragma unroll
+  for (int i = 0; i < IT1; ++i) {
+    const int b = tid + NT * i;
+    if (b < nb1) {
+      const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[i][r] = psi[p * NN + (size_t)(j + Q0 * r) * N + u0 + c];
+    }
+  }
+  const bool ms = tid < CW * QL;
+  const int mc = tid % CW, mj = tid / CW;  // mode-sum thread: column, frequency group
+  float Iv[RL];
+  if (ms) {
+#pragma unroll
+    for (int r = 0; r < RL; ++r) Iv[r] = Ij[(size_t)(mj + QL * r) * N + u0 + mc];
+  }
+  load_twiddles<N, NT>(tw);
+  // forward stage 1 (no twiddles) -> LDS
+#pragma unroll
+  for (int i = 0; i < IT1; ++i) {
+    const int b = tid + NT * i;
+    if (b < nb1) {
+      const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+      dftR<R0, false>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) bufA[(p * CW + c) * PT + j * R0 + r] = v[i][r];
+    }
+  }
+  __syncthreads();
+  // forward stage 2, LDS -> LDS
+  constexpr int MB2 = (MM * CW * (N / R1) + NT - 1) / NT;  // butterflies per thread of stage 2
+  if constexpr (IP) {
+    stage_inplace<N, R1, R0, false, MB2, NT, PT>(bufA, M * CW, tw);
+  } else {
+    stage<N, R1, R0, false, NT, PT>(bufA, bufB, M * CW, tw);
+    __syncthreads();
+  }
+  // forward stage 3 (every mode of one column per thread), modulus,
+  // inverse stage 1
+  double e = 0.0, isv = 0.0;
+  float2 X[MM][RL];
+  if (ms) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        const float2* src = bufB + (p * CW + mc) * PT;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) X[p][r] = src[mj + QL * r];
+      }
+  }
+  if constexpr (IP) lds_barrier();  // every read of the buffer before it is overwritten
+  if (ms) {
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+#pragma unroll
+        for (int r = 1; r < RL; ++r) X[p][r] = cmul(X[p][r], tw[r * mj]);
+        dftR<RL, false>(X[p]);
+      }
+    const float invN = 1.0f / (float)N;
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      float S = 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) S += cabs2(X[p][r]);
+      const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+      const float Au = S * rs;
+      const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv[r], 0.f));
+      const float d = Au * invN - sq;
+      e += (double)d * (double)d;
+      isv += (double)fmaxf(Iv[r], 0.f);
+      bad |= !isfinite(S);
+      const float f = sq * rs * invN;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) X[p][r] = cscale(X[p][r], f);
+    }
+    if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
+#pragma unroll
+    for (int p = 0; p < MM; ++p)
+      if (p < M) {
+        dftR<RL, true>(X[p]);
+        float2* dst = bufA + (p * CW + mc) * PT;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) dst[mj * RL + r] = X[p][r];
+      }
+  }
+  __syncthreads();
+  // inverse stage 2, LDS -> LDS
+  if constexpr (IP) {
+    stage_inplace<N, R1, RL, true, MB2, NT, PT>(bufA, M * CW, tw);
+  } else {
+    stage<N, R1, RL, true, NT, PT>(bufA, bufB, M * CW, tw);
+    __syncthreads();
+  }
+  // inverse stage 3 -> global
+#pragma unroll
+  for (int i = 0; i < IT1; ++i) {
+    const int b = tid + NT * i;
+    if (b < nb1) {
+      const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+      const float2* src = bufB + (p * CW + c) * PT;
+      float2 w8[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) w8[r] = src[j + Q0 * r];
+#pragma unroll
+      for (int r = 1; r < R0; ++r) {
+        float2 w = tw[r * j];
+        w.y = -w.y;
+        w8[r] = cmul(w8[r], w);
+      }
+      dftR<R0, true>(w8);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) psi[p * NN + (size_t)(j + Q0 * r) * N + u0 + c] = w8[r];
+    }
+  }
+  e = wave_sum(e);
+  isv = wave_sum(isv);
+  if ((tid & 63) == 0) {
+    *err_slot = err_old + e;
+    *isum_slot = isum_old + isv;
+  }
+}
+
 // R4: radix-4 FFT plan (else radix 8); MM: register capacity in probe modes
 // (jobs of the launch have M <= MM), so small M does not pay the register
 // cost (and occupancy) of the largest.  `tg` is the launch tick; a job runs
@@ -753,19 +927,23 @@ __global__ __launch_bounds__(256) void k_cols(const LaunchArgs a, int tg) {
   const JobRec& jb = a.job[blockIdx.y];
   const int t = tg - jb.t0;
   constexpr bool RD = !R4 && CW == 1 && !IP;
+  constexpr bool RDW = !R4 && CW > 1;
   switch (jb.N) {
     case 32: cols_body<32, R4, MM, CW, IP>(jb, t, smem); break;
     case 64: cols_body<64, R4, MM, CW, IP>(jb, t, smem); break;
     case 128:
       if constexpr (RD) cols_body_rd<128, MM>(jb, t, smem);
+      else if constexpr (RDW) cols_body_rdw<128, MM, CW, IP>(jb, t, smem);
       else cols_body<128, R4, MM, CW, IP>(jb, t, smem);
       break;
     case 192:
       if constexpr (RD) cols_body_rd<192, MM>(jb, t, smem);
+      else if constexpr (RDW) cols_body_rdw<192, MM, CW, IP>(jb, t, smem);
       else cols_body<192, R4, MM, CW, IP>(jb, t, smem);
       break;
     default:
       if constexpr (RD) cols_body_rd<256, MM>(jb, t, smem);
+      else if constexpr (RDW) cols_body_rdw<256, MM, CW, IP>(jb, t, smem);
       else cols_body<256, R4, MM, CW, IP>(jb, t, smem);
       break;
   }

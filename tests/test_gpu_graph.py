@@ -40,8 +40,9 @@ def test_batched_graph_lanes_of_uneven_jobs():
     """44 jobs of uneven scan length captured as one launch chain: the driver
     deals them to 36 launch lanes, so 8 jobs start when the shorter job ahead
     of them in their lane has taken its last update.  Every replay equals
-    the eager call (two streams of 22 jobs, one lane each) bitwise, and each
-    job matches its plain sweep to float rounding after the first."""
+    the eager call (two streams of 22 jobs, one lane each) bitwise, error
+    curves included, and each job matches its plain sweep to float rounding
+    after the first."""
     from paper_2205_04295_amd import api, graph
     from gpu_util import rel_l2, run_gpu
     specs = []
@@ -50,8 +51,11 @@ def test_batched_graph_lanes_of_uneven_jobs():
         specs.append(dict(seed=150 + i, H=N + 64, N=N, M=1 + (i // 4) % 3, J=2 + (5 * i) % 11))
     ws = [wl.small_case(name=f"l{i}", **s) for i, s in enumerate(specs)]
     prm = dict(ws[0].params, iterations=1)
-    jobs_g = [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"]) for d in map(to_dev, ws)]
-    jobs_e = [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"]) for d in map(to_dev, ws)]
+
+    def jobs():
+        return [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"],
+                     err=torch.zeros(1, dtype=torch.float32, device="cuda:0")) for d in map(to_dev, ws)]
+    jobs_g, jobs_e = jobs(), jobs()
     g = graph.capture_batched(jobs_g, **prm)
     for rep in range(3):
         g.replay()
@@ -60,11 +64,13 @@ def test_batched_graph_lanes_of_uneven_jobs():
         for k, (a, b) in enumerate(zip(jobs_g, jobs_e)):
             assert torch.equal(a["obj"], b["obj"]), (rep, k)
             assert torch.equal(a["probe"], b["probe"]), (rep, k)
+            assert torch.equal(a["err"], b["err"]), (rep, k)
         if rep == 0:
             for w, j in zip(ws, jobs_g):
                 r = run_gpu(w, prm)
                 assert rel_l2(j["obj"].cpu().numpy(), r["O"]) < 1e-5
                 assert rel_l2(j["probe"].cpu().numpy(), r["P"]) < 1e-5
+                assert np.allclose(j["err"].cpu().numpy(), r["err"], rtol=1e-5, atol=0)
 
 
 def test_plain_graph_replays_match_eager():
