@@ -311,6 +311,171 @@ __device__ void adj_p3(const AdjArgs& a, float2* smem) {
   }
 }
 
+// The mode pass for radix-8 three-stage plans (N >= 128) with the first and
+// last FFT stages in registers: each thread loads the inputs of its
+// first-stage butterflies straight from the spectra, the last forward stage
+// leaves each of CW * N / RL threads every mode of one column at RL
+// frequencies, so the loss, the modulus weight and the first inverse stage
+// need no LDS round trip, and the last inverse stage stores straight to the
+// workspace.  The next position's butterfly inputs and pattern values are
+// loaded while the current one's LDS stages run.
+template <int N, int MM, bool IP>
+__device__ void adj_p3_rd(const AdjArgs& a, float2* smem) {
+  using P = Plan8<N>;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2];
+  static_assert(R2 > 1 && P::R[3] == 1, "three-stage plans only");
+  constexpr int CW = kAdjCWM, GRP = adj_p3_group(MM), NT = kAdjThreads;
+  constexpr int RL = R2, Q0 = N / R0, QL = N / RL;
+  constexpr int IT1 = (MM * CW * Q0 + NT - 1) / NT;  // first-stage butterflies per thread
+  static_assert(CW * QL <= NT, "one mode-sum thread per (column, frequency group)");
+  constexpr int PT = col_pitch<N, CW>();             // LDS pitch of a transform
+  constexpr int MB2 = (MM * CW * (N / R1) + NT - 1) / NT;
+  const int u = col_group(gridDim.x), M = a.M;
+  if (u >= N / CW) return;
+  const int b0 = blockIdx.y * GRP, b1 = min(b0 + GRP, a.nb);
+  const int u0 = u * CW, tid = threadIdx.x;
+  const size_t NN = (size_t)N * N;
+  float2* tw = smem;
+  float2* A = tw + N;                    // transform (p, c) at (p * CW + c) * PT
+  float2* B = IP ? A : A + M * CW * PT;
+  const int nb1 = M * CW * Q0;
+  const bool ms = tid < CW * QL;
+  const int mc = tid % CW, mj = tid / CW;  // mode-sum thread: column, frequency group
+  // butterfly b = tid + NT i: column c = b % CW, index j = (b / CW) % Q0 of
+  // transform (p, c), p = b / (CW Q0), rows j + Q0 r
+  float2 nv[IT1][R0];
+  float nI[RL];
+  auto fetch = [&](int bb) {
+    const float2* psi = a.Psi + (size_t)bb * M * NN;
+#pragma unroll
+    for (int i = 0; i < IT1; ++i) {
+      const int b = tid + NT * i;
+      if (b < nb1) {
+        const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) nv[i][r] = psi[p * NN + (size_t)(j + Q0 * r) * N + u0 + c];
+      }
+    }
+    if (ms) {
+      const float* Ij = a.I + (size_t)(a.j0 + bb) * NN;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) nI[r] = Ij[(size_t)(mj + QL * r) * N + u0 + mc];
+    }
+  };
+  if (b0 < b1) fetch(b0);
+  load_twiddles<N, NT>(tw);
+  const float invN = 1.f / (float)N;
+  for (int bb = b0; bb < b1; ++bb) {
+    // forward stage 1 (no twiddles) -> LDS
+#pragma unroll
+    for (int i = 0; i < IT1; ++i) {
+      const int b = tid + NT * i;
+      if (b < nb1) {
+        const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+        dftR<R0, false>(nv[i]);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) A[(p * CW + c) * PT + j * R0 + r] = nv[i][r];
+      }
+    }
+    float Iv[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) Iv[r] = nI[r];
+    if (bb + 1 < b1) fetch(bb + 1);
+    lds_barrier();
+    // forward stage 2
+    if constexpr (IP) {
+      stage_inplace<N, R1, R0, false, MB2, NT, PT>(A, M * CW, tw);
+    } else {
+      stage<N, R1, R0, false, NT, PT>(A, B, M * CW, tw);
+      lds_barrier();
+    }
+    // forward stage 3 (every mode of one column per thread), loss, modulus
+    // weight, inverse stage 1
+    float2 X[MM][RL];
+    if (ms) {
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          const float2* src = B + (p * CW + mc) * PT;
+#pragma unroll
+          for (int r = 0; r < RL; ++r) X[p][r] = src[mj + QL * r];
+        }
+    }
+    if constexpr (IP) lds_barrier();  // every read of the buffer before it is overwritten
+    double e = 0.0;
+    if (ms) {
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+#pragma unroll
+          for (int r = 1; r < RL; ++r) X[p][r] = cmul(X[p][r], tw[r * mj]);
+          dftR<RL, false>(X[p]);
+        }
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        float S = 0.f;
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) S += cabs2(X[p][r]);
+        // hardware reciprocal square root and square root (about 1 ulp)
+        const float rs = S > 0.f ? __builtin_amdgcn_rsqf(S) : 0.f;
+        const float Au = S * rs;
+        const float sq = __builtin_amdgcn_sqrtf(fmaxf(Iv[r], 0.f));
+        const float d = Au * invN - sq;
+        e += (double)d * (double)d;
+        // (1 - sqrt(I)/A) with A = Au / N, and the 1/N^2 of the unnormalised
+        // inverse 2-D transform
+        const float wgt = S > 0.f ? (1.f - sq * (float)N * rs) * invN * invN : 0.f;
+#pragma unroll
+        for (int p = 0; p < MM; ++p)
+          if (p < M) X[p][r] = cscale(X[p][r], wgt);
+      }
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          dftR<RL, true>(X[p]);
+          float2* dst = A + (p * CW + mc) * PT;
+#pragma unroll
+          for (int r = 0; r < RL; ++r) dst[mj * RL + r] = X[p][r];
+        }
+    }
+    lds_barrier();
+    // inverse stage 2
+    if constexpr (IP) {
+      stage_inplace<N, R1, RL, true, MB2, NT, PT>(A, M * CW, tw);
+    } else {
+      stage<N, R1, RL, true, NT, PT>(A, B, M * CW, tw);
+      lds_barrier();
+    }
+    // inverse stage 3 -> the workspace
+    float2* psi = a.Psi + (size_t)bb * M * NN;
+#pragma unroll
+    for (int i = 0; i < IT1; ++i) {
+      const int b = tid + NT * i;
+      if (b < nb1) {
+        const int c = b % CW, j = (b / CW) % Q0, p = b / (CW * Q0);
+        const float2* src = B + (p * CW + c) * PT;
+        float2 w8[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) w8[r] = src[j + Q0 * r];
+#pragma unroll
+        for (int r = 1; r < R0; ++r) {
+          float2 w = tw[r * j];
+          w.y = -w.y;
+          w8[r] = cmul(w8[r], w);
+        }
+        dftR<R0, true>(w8);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) psi[p * NN + (size_t)(j + Q0 * r) * N + u0 + c] = w8[r];
+      }
+    }
+    // one partial per wave, in the slots of the group's CW columns
+    e = wave_sum(e);
+    if ((tid & 63) == 0) a.loss_part[(size_t)bb * N + u0 + (tid >> 6)] = e;
+    lds_barrier();  // this position's reads of the LDS buffers end before the next one's writes
+  }
+}
+
 // P4 (rows): chi row r; g = 2 sum_p conj(P_p) chi_p; the x part of the
 // position gradient from F_x g and F_x o; h = S_{-x}(g) -> G.  A workgroup
 // takes row r of kAdjGroup consecutive positions, kAdjRowPos at a time (each
@@ -526,9 +691,9 @@ __global__ __launch_bounds__(256) void k_adj_p3(const AdjArgs a) {
   switch (a.N) {
     case 32: adj_p3<32, MM, IP>(a, smem); break;
     case 64: adj_p3<64, MM, IP>(a, smem); break;
-    case 128: adj_p3<128, MM, IP>(a, smem); break;
-    case 192: adj_p3<192, MM, IP>(a, smem); break;
-    default: adj_p3<256, MM, IP>(a, smem); break;
+    case 128: adj_p3_rd<128, MM, IP>(a, smem); break;
+    case 192: adj_p3_rd<192, MM, IP>(a, smem); break;
+    default: adj_p3_rd<256, MM, IP>(a, smem); break;
   }
 }
 template <int MM>
