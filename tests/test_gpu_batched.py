@@ -103,6 +103,31 @@ def test_batched_many_jobs_in_place_passes():
     assert rel_l2(jobs[4]["probe"].cpu().numpy(), o["P"]) < 1e-4
 
 
+def test_batched_large_probes_in_place_columns_many_modes():
+    """16 jobs of 192^2 and 256^2 probes with 1, 3 and 5 modes (the column
+    pass runs in place with its first and last stages in registers, for the
+    widest mode capacity too): each job matches its plain sweep to float
+    rounding, and the oracle to the plain sweep's tolerance."""
+    from paper_2205_04295_amd import api
+    specs = [dict(seed=110 + i, H=(192, 256)[i % 2] + 64, N=(192, 256)[i % 2], M=(1, 3, 5)[i % 3], J=3 + i % 3)
+             for i in range(16)]
+    ws = [wl.small_case(name=f"w{i}", **s) for i, s in enumerate(specs)]
+    prm = dict(ws[0].params, iterations=2)
+    devs = [to_dev(w) for w in ws]
+    jobs = [dict(obj=d["obj"], probe=d["probe"], pos=d["pos"], intens=d["I"],
+                 err=torch.zeros(2, dtype=torch.float32, device="cuda:0")) for d in devs]
+    api.rpie_batched(jobs, **prm)
+    torch.cuda.synchronize()
+    for w, j in zip(ws, jobs):
+        g = run_gpu(w, prm)
+        assert rel_l2(j["obj"].cpu().numpy(), g["O"]) < 1e-5
+        assert rel_l2(j["probe"].cpu().numpy(), g["P"]) < 1e-5
+        assert np.allclose(j["err"].cpu().numpy(), g["err"], rtol=1e-5, atol=0)
+    o = run_oracle(ws[5], prm)  # 256^2 x 5 modes
+    assert rel_l2(jobs[5]["obj"].cpu().numpy(), o["O"]) < 1e-4
+    assert rel_l2(jobs[5]["probe"].cpu().numpy(), o["P"]) < 1e-4
+
+
 def test_batched_calls_from_two_host_threads():
     """Two host threads issue batched calls on two streams at once (both fork
     the library's side stream): every job ends bitwise equal to the same call
