@@ -295,15 +295,21 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
 // chain would feel.  The probe is updated in place (each row by the one
 // workgroup that owns it), so no copy-back is needed at the end.
 
-// Update of step t-1 (Eq. 5, Eq. 6) for previous-box row q = blockIdx.x:
-// inverse row FFTs of its spectra, probe row q and object row q from the
-// pre-update o and P.
+// Each split pass takes kSplitRows consecutive rows per workgroup, so every
+// FFT call transforms that many rows of all modes at once (one 256-point row
+// of M modes keeps only 32 M of 256 threads busy in a radix-8 stage).
+constexpr int kSplitRows = 2;
+
+// Update of step t-1 (Eq. 5, Eq. 6) for previous-box rows q0 = kSplitRows
+// blockIdx.x, q0 + 1, ...: inverse row FFTs of their spectra, probe rows and
+// object rows from the pre-update o and P.
 template <int N, bool R4, int MM, bool IP>
 __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
+  constexpr int RP = kSplitRows;
   const int M = jb.M;
   const int total = jb.J * jb.T;
-  const int q = blockIdx.x;
-  if (t < 1 || t > total || q >= N) return;
+  const int q0 = blockIdx.x * RP;
+  if (t < 1 || t > total || q0 >= N) return;
   const int st = t - 1, prv = st & 1;
   const WsLayout L = ws_layout(N, M, jb.T);
   const size_t NN = (size_t)N * N;
@@ -311,84 +317,94 @@ __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int
   const bool lane = tid < N;
   constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch of a transform (padded intermediates)
   float2* tw = smem;
-  float2* bufA = tw + N;
-  float2* bufB = bufA + M * PT;  // ping-pong partner (not used in place)
+  float2* bufA = tw + N;              // transform (s, p) at (s M + p) PT
+  float2* bufB = bufA + RP * M * PT;  // ping-pong partner (not used in place)
   __shared__ float redf[32];
 
   const float2* psi = (const float2*)(jb.ws + pick(L.psi, prv));
   const int jp = st % jb.J;
   const int ny = box_corner(jb.pos[2 * jp], jb.H - N, nullptr);  // flagged by its gather
   const int nx = box_corner(jb.pos[2 * jp + 1], jb.W - N, nullptr);
-  float2* orow = jb.obj + (size_t)(ny + q) * jb.W + nx;
-  float2* prow = jb.probe + (size_t)q * N;
-  float2 pv[MM], Pq[MM];
-  float2 o = make_float2(0.f, 0.f);
+  float2 pv[RP][MM], Pq[RP][MM], o[RP];
   float om_in = 0.f, pm_in = 0.f;
   if (lane) {
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) {
-        pv[p] = psi[p * NN + (size_t)q * N + c];
-        Pq[p] = prow[p * NN + c];
-      }
-    o = orow[c];
+    for (int s = 0; s < RP; ++s) {
+      const int q = q0 + s;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          pv[s][p] = psi[p * NN + (size_t)q * N + c];
+          Pq[s][p] = jb.probe[p * NN + (size_t)q * N + c];
+        }
+      o[s] = jb.obj[(size_t)(ny + q) * jb.W + nx + c];
+    }
     om_in = ((const float*)(jb.ws + pick(L.omax, prv)))[c];
     pm_in = ((const float*)(jb.ws + pick(L.pmax, prv)))[c];
   }
   load_twiddles<N>(tw);
   if (lane) {
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) bufA[p * PT + c] = pv[p];
+    for (int s = 0; s < RP; ++s)
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) bufA[(s * M + p) * PT + c] = pv[s][p];
   }
   float omax, pmaxv;
   block_max2(om_in, pm_in, redf, omax, pmaxv);  // (contains the barrier before the FFT)
   float2* res;
   if constexpr (IP) {
-    fft_lds_inplace<N, true, R4, MM, 256, 0, PT, true>(bufA, M, tw);
+    fft_lds_inplace<N, true, R4, RP * MM, 256, 0, PT, true>(bufA, RP * M, tw);
     res = bufA;
   } else {
-    res = fft_lds<N, true, R4, 0, PT, true>(bufA, bufB, M, tw);
+    res = fft_lds<N, true, R4, 0, PT, true>(bufA, bufB, RP * M, tw);
   }
   const int it_abs = cm.iter_offset + st / jb.J;
   const bool upd_p = it_abs >= cm.probe_update_start;
   bool bad = false;
   if (lane) {
-    const float o2 = cabs2(o);
-    const float dP = cm.beta * omax + (1.f - cm.beta) * o2;
-    const float gP = (upd_p && dP != 0.f) ? cm.alpha_probe / dP : 0.f;
-    float ps = 0.f, Ps = 0.f;
-    float2 num = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) {
-        const float2 P = Pq[p];
-        const float2 d = csub(res[p * PT + c], cmul(P, o));
-        const float2 Pn = cadd(P, cscale(cmulc(d, o), gP));
-        prow[p * NN + c] = Pn;
-        ps += cabs2(Pn);
-        num = cadd(num, cmulc(d, P));
-        Ps += cabs2(P);
-      }
-    bad |= !isfinite(ps);
-    const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
-    const float gO = dO != 0.f ? cm.alpha_obj / dO : 0.f;
-    const float2 on = cadd(o, cscale(num, gO));
-    bad |= !(isfinite(on.x) && isfinite(on.y));
-    orow[c] = on;
+    for (int s = 0; s < RP; ++s) {
+      const int q = q0 + s;
+      const float o2 = cabs2(o[s]);
+      const float dP = cm.beta * omax + (1.f - cm.beta) * o2;
+      const float gP = (upd_p && dP != 0.f) ? cm.alpha_probe / dP : 0.f;
+      float ps = 0.f, Ps = 0.f;
+      float2 num = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          const float2 P = Pq[s][p];
+          const float2 d = csub(res[(s * M + p) * PT + c], cmul(P, o[s]));
+          const float2 Pn = cadd(P, cscale(cmulc(d, o[s]), gP));
+          jb.probe[p * NN + (size_t)q * N + c] = Pn;
+          ps += cabs2(Pn);
+          num = cadd(num, cmulc(d, P));
+          Ps += cabs2(P);
+        }
+      bad |= !isfinite(ps);
+      const float dO = cm.gamma * pmaxv + (1.f - cm.gamma) * Ps;
+      const float gO = dO != 0.f ? cm.alpha_obj / dO : 0.f;
+      const float2 on = cadd(o[s], cscale(num, gO));
+      bad |= !(isfinite(on.x) && isfinite(on.y));
+      jb.obj[(size_t)(ny + q) * jb.W + nx + c] = on;
+    }
   }
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
 }
 
-// Gather of step t for box row r = blockIdx.x: the object row (already
-// updated by step t-1), exit waves with the updated probe row (Eq. 1, 4),
-// the row maxima the next update needs, forward row FFTs into the spectra.
+// Gather of step t for box rows r0 = kSplitRows blockIdx.x, r0 + 1, ...: the
+// object rows (already updated by step t-1), exit waves with the updated
+// probe rows (Eq. 1, 4), the row maxima the next update needs, forward row
+// FFTs into the spectra.
 template <int N, bool R4, int MM, bool IP>
 __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) {
+  constexpr int RP = kSplitRows;
+  static_assert(RP == 2, "the row maxima are reduced as two pairs");
   const int M = jb.M;
   const int total = jb.J * jb.T;
-  const int r = blockIdx.x;
-  if (t < 0 || t >= total || r >= N) return;
+  const int r0 = blockIdx.x * RP;
+  if (t < 0 || t >= total || r0 >= N) return;
   const int cur = t & 1, jn = t % jb.J;
   const WsLayout L = ws_layout(N, M, jb.T);
   const size_t NN = (size_t)N * N;
@@ -396,50 +412,58 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
   const bool lane = tid < N;
   constexpr int PT = col_pitch<N, 1, true>();  // LDS pitch of a transform (padded intermediates)
   float2* tw = smem;
-  float2* bufA = tw + N;
-  float2* bufB = bufA + M * PT;
-  __shared__ float redf[32];
+  float2* bufA = tw + N;              // transform (s, p) at (s M + p) PT
+  float2* bufB = bufA + RP * M * PT;
+  __shared__ float redf[64];
 
   const int ny = box_corner(jb.pos[2 * jn], jb.H - N, jb.status);
   const int nx = box_corner(jb.pos[2 * jn + 1], jb.W - N, jb.status);
-  float2 o = make_float2(0.f, 0.f);
-  float2 Pn[MM];
+  float2 o[RP], Pn[RP][MM];
   if (lane) {
-    o = jb.obj[(size_t)(ny + r) * jb.W + nx + c];
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) Pn[p] = jb.probe[p * NN + (size_t)r * N + c];
+    for (int s = 0; s < RP; ++s) {
+      o[s] = jb.obj[(size_t)(ny + r0 + s) * jb.W + nx + c];
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) Pn[s][p] = jb.probe[p * NN + (size_t)(r0 + s) * N + c];
+    }
   }
   load_twiddles<N>(tw);
-  float om = 0.f, pm_row = 0.f;
+  float om[RP] = {}, pm_row[RP] = {};
   if (lane) {
-    om = cabs2(o);
-    float ps = 0.f;
 #pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) {
-        ps += cabs2(Pn[p]);
-        bufA[p * PT + c] = cmul(Pn[p], o);
-      }
-    pm_row = ps;
+    for (int s = 0; s < RP; ++s) {
+      om[s] = cabs2(o[s]);
+      float ps = 0.f;
+#pragma unroll
+      for (int p = 0; p < MM; ++p)
+        if (p < M) {
+          ps += cabs2(Pn[s][p]);
+          bufA[(s * M + p) * PT + c] = cmul(Pn[s][p], o[s]);
+        }
+      pm_row[s] = ps;
+    }
   }
-  float pm;
-  block_max2(om, pm_row, redf, om, pm);  // (its barriers also publish bufA)
+  float om0, pm0, om1, pm1;
+  block_max2(om[0], pm_row[0], redf, om0, pm0);  // (its barriers also publish bufA)
+  block_max2(om[1], pm_row[1], redf + 32, om1, pm1);
   if (tid == 0) {
-    ((float*)(jb.ws + pick(L.omax, cur)))[r] = om;
-    ((float*)(jb.ws + pick(L.pmax, cur)))[r] = pm;
+    ((float*)(jb.ws + pick(L.omax, cur)))[r0] = om0;
+    ((float*)(jb.ws + pick(L.pmax, cur)))[r0] = pm0;
+    ((float*)(jb.ws + pick(L.omax, cur)))[r0 + 1] = om1;
+    ((float*)(jb.ws + pick(L.pmax, cur)))[r0 + 1] = pm1;
   }
   float2* res;
   if constexpr (IP) {
-    fft_lds_inplace<N, false, R4, MM, 256, 0, PT, true>(bufA, M, tw);
+    fft_lds_inplace<N, false, R4, RP * MM, 256, 0, PT, true>(bufA, RP * M, tw);
     res = bufA;
   } else {
-    res = fft_lds<N, false, R4, 0, PT, true>(bufA, bufB, M, tw);
+    res = fft_lds<N, false, R4, 0, PT, true>(bufA, bufB, RP * M, tw);
   }
   float2* dst = (float2*)(jb.ws + pick(L.psi, cur));
-  for (int i = tid; i < M * N; i += blockDim.x) {
-    const int p = i / N, cc = i - p * N;
-    dst[p * NN + (size_t)r * N + cc] = res[p * PT + cc];
+  for (int i = tid; i < RP * M * N; i += blockDim.x) {
+    const int sp = i / N, cc = i - sp * N, s = sp / M, p = sp - s * M;
+    dst[p * NN + (size_t)(r0 + s) * N + cc] = res[sp * PT + cc];
   }
 }
 
@@ -1208,7 +1232,9 @@ static size_t cols_lds(int N, int M, int cw, bool inplace) {
   const int pitch = cw > 1 ? base + 16 / cw : base;
   return (size_t)(N + (inplace ? 1 : 2) * cw * M * pitch) * 8;
 }
-static size_t split_lds(int N, int M, bool inplace) { return (size_t)(N + (inplace ? 1 : 2) * M * row_pitch(N)) * 8; }
+static size_t split_lds(int N, int M, bool inplace) {
+  return (size_t)(N + (inplace ? 1 : 2) * kSplitRows * M * row_pitch(N)) * 8;
+}
 
 // The column pass runs in place with the row pass only in calls of this many
 // jobs or more: it doubles the workgroups per CU but adds a barrier per
@@ -1384,9 +1410,9 @@ static void launch_tick(PassGroup& g, const Common& c, int t) {
   TickTables tt;
   tick_tables(g, c, t, tt);
   if (g.split) {
-    if (tt.upd.njobs) launch_k(TK_UPD, g.ku, dim3(tt.upd_n, tt.upd.njobs), g.rblk, g.lu, g.s, tt.upd, t);
+    if (tt.upd.njobs) launch_k(TK_UPD, g.ku, dim3(tt.upd_n / kSplitRows, tt.upd.njobs), g.rblk, g.lu, g.s, tt.upd, t);
     if (tt.nxt.njobs) {
-      launch_k(TK_GAT, g.kg, dim3(tt.nxt_n, tt.nxt.njobs), g.rblk, g.lu, g.s, tt.nxt, t);
+      launch_k(TK_GAT, g.kg, dim3(tt.nxt_n / kSplitRows, tt.nxt.njobs), g.rblk, g.lu, g.s, tt.nxt, t);
       launch_k(TK_COLS, g.kc, dim3(tt.nxt_n / g.width, tt.nxt.njobs), blk, g.lc, g.s, tt.nxt, t);
     }
     return;
