@@ -136,7 +136,7 @@ def test_full_size_subpixel_step_teacher_forced(refine_w, k, refine, up):
 def spiral_oracle_run(spiral, request):
     """The FP64 oracle on the whole workload for 20 iterations (one call per
     iteration, the state after iterations 1 and 20 kept).  About 13 s per
-    iteration on the GPU machine's host; one line per finished iteration."""
+    iteration on one host core; one line per finished iteration."""
     cap = request.config.pluginmanager.getplugin("capturemanager")
     w = spiral
     prm = dict(w.params, iterations=1)
