@@ -669,6 +669,102 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
   if (tid < CW && a.subpixel) a.pos_part[((size_t)b * N + u0 + tid) * kPosSlots] = tid == 0 ? gy : 0.0;
 }
 
+// P1 for radix-8 three-stage plans (N >= 128) with the first and last FFT
+// stages in registers, kAdjCWR columns per workgroup: the first stage takes
+// the global loads, the last forward stage leaves each of kAdjCWR * N / RL
+// threads one column at RL frequencies, where the ramp and the first
+// inverse stage run without an LDS round trip, and the last inverse stage
+// stores straight to the workspace.  (The same for P5, with two fields per
+// column, was slower than its staged version: 111.6 against 102.0 us per
+// 256 positions at 256^2.)
+constexpr int kAdjCWR = 4;
+
+template <int N>
+struct AdjRd {
+  using P = Plan8<N>;
+  static constexpr int R0 = P::R[0], R1 = P::R[1], RL = P::R[2];
+  static_assert(RL > 1 && P::R[3] == 1, "three-stage plans only");
+  static constexpr int Q0 = N / R0, QL = N / RL, CW = kAdjCWR;
+  static constexpr int PT = col_pitch<N, CW>();  // LDS pitch of a transform
+  static_assert(CW * QL <= kAdjThreads, "one ramp thread per (column, frequency group)");
+};
+
+template <int N>
+__device__ void adj_p1_rd(const AdjArgs& a, float2* smem) {
+  using D = AdjRd<N>;
+  constexpr int R0 = D::R0, R1 = D::R1, RL = D::RL, Q0 = D::Q0, QL = D::QL, CW = D::CW, PT = D::PT;
+  constexpr int NT = kAdjThreads;
+  const int u = col_group(gridDim.x), b = blockIdx.y;
+  if (u >= N / CW) return;
+  const int u0 = u * CW, j = a.j0 + b, tid = threadIdx.x;
+  const int ny = box_corner(a.pos[2 * j], a.H - N, a.status);
+  const int nx = box_corner(a.pos[2 * j + 1], a.W - N, a.status);
+  float fy, fx;
+  frac_of(a, j, N, &fy, &fx);
+  float2* tw = smem;
+  float2* A = tw + N;       // transform c at c * PT
+  float2* B = A + CW * PT;
+  // first-stage butterfly tid: column c = tid % CW, index jj = tid / CW
+  const bool s1 = tid < CW * Q0;
+  const int c1 = tid % CW, j1 = tid / CW;
+  float2 v[R0];
+  if (s1) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = a.obj[(size_t)(ny + j1 + Q0 * r) * a.W + nx + u0 + c1];
+  }
+  load_twiddles<N, NT>(tw);
+  if (s1) {
+    dftR<R0, false>(v);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) A[c1 * PT + j1 * R0 + r] = v[r];
+  }
+  __syncthreads();
+  stage<N, R1, R0, false, NT, PT>(A, B, CW, tw);
+  __syncthreads();
+  // last forward stage, the ramp e^{+2 pi i ky fy / N} / N, first inverse stage
+  const bool ms = tid < CW * QL;
+  const int mc = tid % CW, mj = tid / CW;
+  if (ms) {
+    float2 X[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) X[r] = B[mc * PT + mj + QL * r];
+#pragma unroll
+    for (int r = 1; r < RL; ++r) X[r] = cmul(X[r], tw[r * mj]);
+    dftR<RL, false>(X);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int k = mj + QL * r, ky = k < N / 2 ? k : k - N;
+      X[r] = cscale(cmul(X[r], ramp(ky, 0, fy, 0.f, 1.f, N)), 1.f / (float)N);
+    }
+    dftR<RL, true>(X);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) A[mc * PT + mj * RL + r] = X[r];
+  }
+  __syncthreads();
+  stage<N, R1, RL, true, NT, PT>(A, B, CW, tw);
+  __syncthreads();
+  if (s1) {
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = B[c1 * PT + j1 + Q0 * r];
+#pragma unroll
+    for (int r = 1; r < R0; ++r) {
+      float2 w = tw[r * j1];
+      w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dftR<R0, true>(v);
+    float2* cp = a.Cp + chunk_off(b, N);
+#pragma unroll
+    for (int r = 0; r < R0; ++r) cp[(size_t)(j1 + Q0 * r) * N + u0 + c1] = v[r];
+  }
+}
+
+template <int N>
+__device__ void adj_p1_any(const AdjArgs& a, float2* smem) {
+  if constexpr (N >= 128) adj_p1_rd<N>(a, smem);
+  else adj_p1<N>(a, smem);
+}
+
 #define MRPIE_ADJ_KERNEL(NAME, FN)                       \
   __global__ __launch_bounds__(256) void NAME(const AdjArgs a) { \
     extern __shared__ float2 smem[];                     \
@@ -680,7 +776,7 @@ __device__ void adj_p5(const AdjArgs& a, float2* smem) {
       default: FN<256>(a, smem); break;                  \
     }                                                    \
   }
-MRPIE_ADJ_KERNEL(k_adj_p1, adj_p1)
+MRPIE_ADJ_KERNEL(k_adj_p1, adj_p1_any)
 MRPIE_ADJ_KERNEL(k_adj_p2, adj_p2)
 // the mode pass per bound MM >= M on the modes (register arrays of the
 // in-place transforms)
@@ -860,7 +956,12 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
   const size_t l2 = (N + 2 * kAdjRowPos * M * pr) * 8, l4 = (N + 2 * kAdjRowPos * std::max(M, 2) * pr) * 8;
   const size_t pbase = pr, p1 = pbase + 16 / kAdjCW1, pm = pbase + 16 / kAdjCWM;
   const size_t lc1 = (size_t)(N + 2 * kAdjCW1 * p1) * 8, lcm = (size_t)(N + (M <= 4 ? 1 : 2) * M * kAdjCWM * pm) * 8;
-  MRPIE_HIP(ensure_lds((const void*)k_adj_p1, lc1));
+  // from N = 128 P1 takes kAdjCWR columns per workgroup at the pitch
+  // N + 16 / kAdjCWR
+  const bool rd = N >= 128;
+  const int cw1 = rd ? kAdjCWR : kAdjCW1;
+  const size_t lp1 = rd ? (N + 2 * kAdjCWR * ((size_t)N + 16 / kAdjCWR)) * 8 : lc1;
+  MRPIE_HIP(ensure_lds((const void*)k_adj_p1, lp1));
   MRPIE_HIP(ensure_lds((const void*)k_adj_p2, l2));
   const auto kp4 = M <= 1 ? k_adj_p4<1> : M <= 2 ? k_adj_p4<2> : M <= 4 ? k_adj_p4<4> : k_adj_p4<MRPIE_MAX_MODES>;
   MRPIE_HIP(ensure_lds((const void*)kp4, l4));
@@ -872,8 +973,8 @@ int run_adjoint(const mrpie_problem* pb, int subpixel, const float2* obj, const 
     const int nb = std::min(L.chunk, J - j0);
     a.j0 = j0;
     a.nb = nb;
-    const dim3 g1(N / kAdjCW1, nb), blk(kAdjThreads);
-    hipLaunchKernelGGL(k_adj_p1, g1, blk, lc1, s, a);
+    const dim3 gp1(N / cw1, nb), g1(N / kAdjCW1, nb), blk(kAdjThreads);
+    hipLaunchKernelGGL(k_adj_p1, gp1, blk, lp1, s, a);
     hipLaunchKernelGGL(k_adj_p2, dim3(N, (nb + kAdjRowPos - 1) / kAdjRowPos), blk, l2, s, a);
     launch_ku(TK_ADJ, nb, kp3, dim3(N / kAdjCWM, (nb + g3 - 1) / g3), blk, lcm, s, a);  // timed per position
     hipLaunchKernelGGL(k_adj_loss_part, dim3(kLossBlocks), blk, 0, s, a, nb);
