@@ -39,20 +39,20 @@ FP32_VALU_PEAK_TFS = 78.6
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "50406081e80f61230a15f3ef39b7c1653d7d263902114c165936318cb88e6220",
+    "sha256": "50e7040b07d2ded73468f7972086e53a64224e4ae948203d4aa6a109f34f5988",
     "fetch_factor": 2.000, "write_factor": 1.000,
     ("k_rows", 1): {"fetch_kib": 3457.5, "write_kib": 4097.6},
     ("k_cols", 1): {"fetch_kib": 998.0, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13004.9, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3702.6, "write_kib": 6160.0},
-    ("k_rows", 8): {"fetch_kib": 26202.4, "write_kib": 32780.7},
-    ("k_cols", 8): {"fetch_kib": 7297.0, "write_kib": 12320.0},
-    ("k_upd", 16): {"fetch_kib": 29143.9, "write_kib": 32865.3},
-    ("k_gat", 16): {"fetch_kib": 16721.4, "write_kib": 24832.1},
-    ("k_cols", 16): {"fetch_kib": 14498.5, "write_kib": 24640.1},
-    ("k_upd", 32): {"fetch_kib": 58202.7, "write_kib": 65730.6},
-    ("k_gat", 32): {"fetch_kib": 33363.8, "write_kib": 49664.4},
-    ("k_cols", 32): {"fetch_kib": 28919.6, "write_kib": 51735.4},
+    ("k_rows", 4): {"fetch_kib": 13005.7, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3707.6, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 26222.2, "write_kib": 32780.7},
+    ("k_cols", 8): {"fetch_kib": 7302.0, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29185.6, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16734.2, "write_kib": 24704.0},
+    ("k_cols", 16): {"fetch_kib": 14506.5, "write_kib": 24640.1},
+    ("k_upd", 32): {"fetch_kib": 58249.3, "write_kib": 65730.8},
+    ("k_gat", 32): {"fetch_kib": 33377.6, "write_kib": 49410.7},
+    ("k_cols", 32): {"fetch_kib": 28995.5, "write_kib": 52552.0},
 }
 
 
