@@ -295,17 +295,19 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
 // chain would feel.  The probe is updated in place (each row by the one
 // workgroup that owns it), so no copy-back is needed at the end.
 
-// Each split pass takes kSplitRows consecutive rows per workgroup, so every
-// FFT call transforms that many rows of all modes at once (one 256-point row
-// of M modes keeps only 32 M of 256 threads busy in a radix-8 stage).
-constexpr int kSplitRows = 2;
+// Each split pass of mode capacity MM <= 4 takes two consecutive rows per
+// workgroup, so every FFT call transforms 2M rows at once (one 256-point row
+// of M modes keeps only 32 M of 256 threads busy in a radix-8 stage); with
+// MM = 8 the doubled register arrays would cost more occupancy than that
+// gains, so it keeps one.
+__host__ __device__ constexpr int split_rows(int mm) { return mm <= 4 ? 2 : 1; }
 
-// Update of step t-1 (Eq. 5, Eq. 6) for previous-box rows q0 = kSplitRows
+// Update of step t-1 (Eq. 5, Eq. 6) for previous-box rows q0 = split_rows(MM)
 // blockIdx.x, q0 + 1, ...: inverse row FFTs of their spectra, probe rows and
 // object rows from the pre-update o and P.
 template <int N, bool R4, int MM, bool IP>
 __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int t, float2* smem) {
-  constexpr int RP = kSplitRows;
+  constexpr int RP = split_rows(MM);
   const int M = jb.M;
   const int total = jb.J * jb.T;
   const int q0 = blockIdx.x * RP;
@@ -393,14 +395,13 @@ __device__ __forceinline__ void upd_body(const Common& cm, const JobRec& jb, int
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
 }
 
-// Gather of step t for box rows r0 = kSplitRows blockIdx.x, r0 + 1, ...: the
+// Gather of step t for box rows r0 = split_rows(MM) blockIdx.x, r0 + 1, ...: the
 // object rows (already updated by step t-1), exit waves with the updated
 // probe rows (Eq. 1, 4), the row maxima the next update needs, forward row
 // FFTs into the spectra.
 template <int N, bool R4, int MM, bool IP>
 __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) {
-  constexpr int RP = kSplitRows;
-  static_assert(RP == 2, "the row maxima are reduced as two pairs");
+  constexpr int RP = split_rows(MM);
   const int M = jb.M;
   const int total = jb.J * jb.T;
   const int r0 = blockIdx.x * RP;
@@ -444,14 +445,16 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
       pm_row[s] = ps;
     }
   }
-  float om0, pm0, om1, pm1;
-  block_max2(om[0], pm_row[0], redf, om0, pm0);  // (its barriers also publish bufA)
-  block_max2(om[1], pm_row[1], redf + 32, om1, pm1);
+  float omr[RP], pmr[RP];
+#pragma unroll
+  for (int s = 0; s < RP; ++s)  // (the first reduction's barriers also publish bufA)
+    block_max2(om[s], pm_row[s], redf + 32 * s, omr[s], pmr[s]);
   if (tid == 0) {
-    ((float*)(jb.ws + pick(L.omax, cur)))[r0] = om0;
-    ((float*)(jb.ws + pick(L.pmax, cur)))[r0] = pm0;
-    ((float*)(jb.ws + pick(L.omax, cur)))[r0 + 1] = om1;
-    ((float*)(jb.ws + pick(L.pmax, cur)))[r0 + 1] = pm1;
+#pragma unroll
+    for (int s = 0; s < RP; ++s) {
+      ((float*)(jb.ws + pick(L.omax, cur)))[r0 + s] = omr[s];
+      ((float*)(jb.ws + pick(L.pmax, cur)))[r0 + s] = pmr[s];
+    }
   }
   float2* res;
   if constexpr (IP) {
@@ -1232,8 +1235,8 @@ static size_t cols_lds(int N, int M, int cw, bool inplace) {
   const int pitch = cw > 1 ? base + 16 / cw : base;
   return (size_t)(N + (inplace ? 1 : 2) * cw * M * pitch) * 8;
 }
-static size_t split_lds(int N, int M, bool inplace) {
-  return (size_t)(N + (inplace ? 1 : 2) * kSplitRows * M * row_pitch(N)) * 8;
+static size_t split_lds(int N, int M, bool inplace, int rows) {
+  return (size_t)(N + (inplace ? 1 : 2) * rows * M * row_pitch(N)) * 8;
 }
 
 // The column pass runs in place with the row pass only in calls of this many
@@ -1267,6 +1270,7 @@ struct PassGroup {
   int maxTot = 0;  // last tick of the group
   bool single = false;  // a single-job call: the scalar-argument kernels
   bool split = false;   // update / gather / column launches per position
+  int srows = 1;        // rows per workgroup of the split passes
   int width = 1;
   size_t lr = 0, lc = 0, lu = 0;
   dim3 rblk;
@@ -1345,7 +1349,8 @@ static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* job
   if (rc) return rc;
   if (tu.rows_split) {
     g.split = true;
-    for (const JobRec& jb : g.jobs) g.lu = std::max(g.lu, split_lds(jb.N, jb.M, ip));
+    g.srows = split_rows(mode_class(maxM));
+    for (const JobRec& jb : g.jobs) g.lu = std::max(g.lu, split_lds(jb.N, jb.M, ip, g.srows));
     g.ku = upd_kernel(tu.rows_radix, ip, maxM);
     g.kg = gat_kernel(tu.rows_radix, ip, maxM);
     g.kc = cols_kernel(tu.cols_radix, tu.cols_width, cip, maxM);
@@ -1410,9 +1415,9 @@ static void launch_tick(PassGroup& g, const Common& c, int t) {
   TickTables tt;
   tick_tables(g, c, t, tt);
   if (g.split) {
-    if (tt.upd.njobs) launch_k(TK_UPD, g.ku, dim3(tt.upd_n / kSplitRows, tt.upd.njobs), g.rblk, g.lu, g.s, tt.upd, t);
+    if (tt.upd.njobs) launch_k(TK_UPD, g.ku, dim3(tt.upd_n / g.srows, tt.upd.njobs), g.rblk, g.lu, g.s, tt.upd, t);
     if (tt.nxt.njobs) {
-      launch_k(TK_GAT, g.kg, dim3(tt.nxt_n / kSplitRows, tt.nxt.njobs), g.rblk, g.lu, g.s, tt.nxt, t);
+      launch_k(TK_GAT, g.kg, dim3(tt.nxt_n / g.srows, tt.nxt.njobs), g.rblk, g.lu, g.s, tt.nxt, t);
       launch_k(TK_COLS, g.kc, dim3(tt.nxt_n / g.width, tt.nxt.njobs), blk, g.lc, g.s, tt.nxt, t);
     }
     return;
