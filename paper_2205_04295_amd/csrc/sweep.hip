@@ -1025,6 +1025,10 @@ using RowsKernel1 = void (*)(char*, float2*, float2*, const float*, int, int, in
 using ColsKernel1 = void (*)(char*, const float*, int, int, int, int, int*);
 
 static int mode_class(int M) { return M <= 1 ? 1 : M <= 2 ? 2 : M <= 4 ? 4 : 8; }
+// Register capacity of the multi-job kernels: one more class for 5 or 6
+// modes, so batches whose largest job has 5 modes (a common mix) do not pay
+// the register arrays (and occupancy) of 8.
+static int batch_mode_class(int M) { return M <= 4 ? mode_class(M) : M <= 6 ? 6 : 8; }
 
 template <bool R4, bool IP>
 static SweepKernel pick_rows(int mc) {
@@ -1032,6 +1036,7 @@ static SweepKernel pick_rows(int mc) {
     case 1: return k_rows<R4, 1, IP>;
     case 2: return k_rows<R4, 2, IP>;
     case 4: return k_rows<R4, 4, IP>;
+    case 6: return k_rows<R4, 6, IP>;
     default: return k_rows<R4, 8, IP>;
   }
 }
@@ -1041,6 +1046,7 @@ static SweepKernel pick_cols(int mc) {
     case 1: return k_cols<R4, 1, CW, IP>;
     case 2: return k_cols<R4, 2, CW, IP>;
     case 4: return k_cols<R4, 4, CW, IP>;
+    case 6: return k_cols<R4, 6, CW, IP>;
     default: return k_cols<R4, 8, CW, IP>;
   }
 }
@@ -1050,6 +1056,7 @@ static SweepKernel pick_upd(int mc) {
     case 1: return k_upd<R4, 1, IP>;
     case 2: return k_upd<R4, 2, IP>;
     case 4: return k_upd<R4, 4, IP>;
+    case 6: return k_upd<R4, 6, IP>;
     default: return k_upd<R4, 8, IP>;
   }
 }
@@ -1059,6 +1066,7 @@ static SweepKernel pick_gat(int mc) {
     case 1: return k_gat<R4, 1, IP>;
     case 2: return k_gat<R4, 2, IP>;
     case 4: return k_gat<R4, 4, IP>;
+    case 6: return k_gat<R4, 6, IP>;
     default: return k_gat<R4, 8, IP>;
   }
 }
@@ -1089,23 +1097,23 @@ static ColsKernel1 cols_kernel1(int radix, int width, int M) {
   return radix == 8 ? pick_cols1<false, 1>(mc) : pick_cols1<true, 1>(mc);
 }
 static SweepKernel rows_kernel(int radix, bool inplace, int maxM) {
-  const int mc = mode_class(maxM);
+  const int mc = batch_mode_class(maxM);
   if (inplace) return radix == 8 ? pick_rows<false, true>(mc) : pick_rows<true, true>(mc);
   return radix == 8 ? pick_rows<false, false>(mc) : pick_rows<true, false>(mc);
 }
 static SweepKernel upd_kernel(int radix, bool inplace, int maxM) {
-  const int mc = mode_class(maxM);
+  const int mc = batch_mode_class(maxM);
   if (inplace) return radix == 8 ? pick_upd<false, true>(mc) : pick_upd<true, true>(mc);
   return radix == 8 ? pick_upd<false, false>(mc) : pick_upd<true, false>(mc);
 }
 static SweepKernel gat_kernel(int radix, bool inplace, int maxM) {
-  const int mc = mode_class(maxM);
+  const int mc = batch_mode_class(maxM);
   if (inplace) return radix == 8 ? pick_gat<false, true>(mc) : pick_gat<true, true>(mc);
   return radix == 8 ? pick_gat<false, false>(mc) : pick_gat<true, false>(mc);
 }
 // multi-job launches; in place only with 4 columns per workgroup
 static SweepKernel cols_kernel(int radix, int width, bool inplace, int maxM) {
-  const int mc = mode_class(maxM);
+  const int mc = batch_mode_class(maxM);
   if (width == 4 && inplace) return radix == 8 ? pick_cols<false, 4, true>(mc) : pick_cols<true, 4, true>(mc);
   if (width == 4) return radix == 8 ? pick_cols<false, 4, false>(mc) : pick_cols<true, 4, false>(mc);
   return radix == 8 ? pick_cols<false, 1, false>(mc) : pick_cols<true, 1, false>(mc);
@@ -1178,7 +1186,8 @@ __global__ void k_probe_back(const LaunchArgs a) {
 // against 164 us), ping-pong for a single sweep.  The
 // autotuner measures the alternatives on the device for any (N, M, batch).
 // Per (N, mode class, batch class); mode classes M = 1, 2, 3-4, 5-8 (the
-// register capacity the kernels are compiled for).
+// single-job kernels' register capacities; the multi-job kernels split the
+// last class into 5-6 and 7-8).
 static Tuning g_tune[5][4][3];
 static bool g_tune_set[5][4][3];
 static std::mutex g_tune_mu;
@@ -1349,7 +1358,7 @@ static int prepare_group(PassGroup& g, const Common& c, const JobRec* const* job
   if (rc) return rc;
   if (tu.rows_split) {
     g.split = true;
-    g.srows = split_rows(mode_class(maxM));
+    g.srows = split_rows(batch_mode_class(maxM));
     for (const JobRec& jb : g.jobs) g.lu = std::max(g.lu, split_lds(jb.N, jb.M, ip, g.srows));
     g.ku = upd_kernel(tu.rows_radix, ip, maxM);
     g.kg = gat_kernel(tu.rows_radix, ip, maxM);
