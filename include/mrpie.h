@@ -263,7 +263,8 @@ int mrpie_rpie_batched(int32_t njobs, const mrpie_job* jobs, const mrpie_params*
 /* Autotuner of the launch shapes for probe size N, the mode class of M and
  * the call class of `batch` jobs (1: single mrpie_rpie calls; 2-15 and
  * 16 or more: the two classes of mrpie_rpie_batched calls).  mrpie_autotune fills its workspace with `batch`
- * synthetic problems of shape (N, M, J positions, object 3N x 3N), runs one
+ * synthetic problems of shape (N, M, J positions along a Fermat spiral with
+ * about 70 % overlap between consecutive probes, object 3N x 3N), runs one
  * sweep iteration with every candidate (mrpie_tuning_candidates lists them,
  * in order) in reps + 1 round-robin rounds on `stream` (the first round warms
  * up), timed with HIP events, keeps each candidate's fastest timed run,

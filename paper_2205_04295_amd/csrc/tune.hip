@@ -64,8 +64,19 @@ __global__ void k_tune_fill(char* base, size_t job_bytes, size_t o_obj, size_t o
         make_float2(hash01(seed + 7u * (unsigned)i) - 0.5f, hash01(seed + 7u * (unsigned)i + 3u) - 0.5f);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nI; i += stride)
     ((float*)(jb + o_I))[i] = 2.0f * (float)M * hash01(seed * 31u + (unsigned)i);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)2 * J; i += stride)
-    ((float*)(jb + o_pos))[i] = floorf(hash01(seed * 17u + (unsigned)i) * (float)(H - N + 1) * 0.999f);
+  // positions along a Fermat spiral around the object's centre (golden-angle
+  // steps of about 0.04 N: the ~70 % overlap of consecutive probes of the
+  // paper's scans, shrunk for long runs so the spiral stays inside), the
+  // scan pattern whose box moves the row passes are built for
+  const float c0 = fminf(0.0394f * (float)N, 0.95f * (float)(H - N) / (2.f * sqrtf((float)J)));
+  const float ctr = 0.5f * (float)(H - N);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)J; i += stride) {
+    const float r = c0 * sqrtf((float)i), th = 2.39996323f * (float)i;  // golden angle in radians
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    ((float*)(jb + o_pos))[2 * i] = floorf(ctr + r * sn + 0.5f);
+    ((float*)(jb + o_pos))[2 * i + 1] = floorf(ctr + r * cs + 0.5f);
+  }
 }
 
 int candidates(int N, int M, bool batched, std::vector<Tuning>& out) {
