@@ -570,10 +570,12 @@ def main():
     tuned = None
     if args.autotune:
         from paper_2205_04295_amd import tune
-        # best of several short runs per candidate: close candidates (the
-        # in-place option at 8 jobs) are otherwise decided by timing noise
+        # best of several runs per candidate: close candidates (the in-place
+        # and split options at 8 jobs) are otherwise decided by timing noise;
+        # the 8-job runs are 512 positions long (at 128 the split pass with
+        # radix-8 rows, about 9 % slower on the full workload, timed fastest)
         tuned = {"plain": tune.autotune(N, M, batch=1, J=128, reps=4)[0],
-                 "batched": tune.autotune(N, M, batch=max(2, args.batch), J=128, reps=5)[0]}
+                 "batched": tune.autotune(N, M, batch=max(2, args.batch), J=512, reps=5)[0]}
         if args.batch_large >= 16:
             tuned["batched_large"] = tune.autotune(N, M, batch=args.batch_large, J=64, reps=3)[0]
     ws = None
