@@ -39,20 +39,20 @@ FP32_VALU_PEAK_TFS = 78.6
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "d33797f0d7ad2c6d2916936191aa417b6ccb8adba8d389214a95bb7651049b43",
+    "sha256": "f90e5f8f8421f78966e6fff9cbeaa9e89919f8d273a93b2918e567b644add8fe",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    ("k_rows", 1): {"fetch_kib": 3449.5, "write_kib": 4097.6},
-    ("k_cols", 1): {"fetch_kib": 1000.0, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13010.8, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3710.6, "write_kib": 6160.0},
-    ("k_rows", 8): {"fetch_kib": 26158.7, "write_kib": 32780.7},
-    ("k_cols", 8): {"fetch_kib": 7305.0, "write_kib": 12320.0},
-    ("k_upd", 16): {"fetch_kib": 29184.9, "write_kib": 32865.3},
-    ("k_gat", 16): {"fetch_kib": 16734.6, "write_kib": 24704.0},
-    ("k_cols", 16): {"fetch_kib": 14507.7, "write_kib": 24640.5},
-    ("k_upd", 32): {"fetch_kib": 58247.8, "write_kib": 65730.9},
-    ("k_gat", 32): {"fetch_kib": 33378.1, "write_kib": 49411.1},
-    ("k_cols", 32): {"fetch_kib": 28973.5, "write_kib": 52677.7},
+    ("k_rows", 1): {"fetch_kib": 3457.5, "write_kib": 4097.6},
+    ("k_cols", 1): {"fetch_kib": 995.5, "write_kib": 1552.0},
+    ("k_rows", 4): {"fetch_kib": 13010.9, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3700.1, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 26008.1, "write_kib": 32780.7},
+    ("k_cols", 8): {"fetch_kib": 7294.5, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29180.9, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16731.8, "write_kib": 24704.0},
+    ("k_cols", 16): {"fetch_kib": 14503.4, "write_kib": 24640.2},
+    ("k_upd", 32): {"fetch_kib": 58242.8, "write_kib": 65731.0},
+    ("k_gat", 32): {"fetch_kib": 33374.9, "write_kib": 49411.2},
+    ("k_cols", 32): {"fetch_kib": 28948.2, "write_kib": 52351.8},
 }
 
 
