@@ -226,6 +226,54 @@ __device__ C* fft_lds(C* a, C* b, int nb, const C* __restrict__ tw) {
   return a;
 }
 
+// fft_lds whose last stage hands its outputs to `store(t, k, v)` (element k
+// of transform t) instead of writing them to LDS: the caller's global
+// stores leave from registers, without the last LDS round trip and barrier.
+template <int N, bool INV, bool R4 = true, int NT = 0, int PITCH = N, bool PAD = false, typename C, typename S>
+__device__ void fft_lds_store(C* a, C* b, int nb, const C* __restrict__ tw, S store) {
+  using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
+  constexpr int NS = R3 > 1 ? R0 * R1 * R2 : R2 > 1 ? R0 * R1 : R0;  // span before the last stage
+  constexpr int RL = R3 > 1 ? R3 : R2 > 1 ? R2 : R1;                // last radix
+  static_assert(NS * RL == N, "plan covers N");
+  const C* src;
+  stage<N, R0, 1, INV, NT, PITCH, false, PAD>(a, b, nb, tw);
+  lds_barrier();
+  if constexpr (R2 == 1) {
+    src = b;
+  } else {
+    stage<N, R1, R0, INV, NT, PITCH, PAD, PAD>(b, a, nb, tw);
+    lds_barrier();
+    if constexpr (R3 == 1) {
+      src = a;
+    } else {
+      stage<N, R2, R0 * R1, INV, NT, PITCH, PAD, PAD>(a, b, nb, tw);
+      lds_barrier();
+      src = b;
+    }
+  }
+  // last stage: butterfly j < NS of transform t reads j + NS r, writes the
+  // natural-order outputs j + NS r
+  constexpr int TWS = 1;  // N / (NS * RL)
+  const int total = nb * NS;
+  for (int q = threadIdx.x; q < total; q += wg_threads<NT>()) {
+    const int t = q / NS, j = q - t * NS;
+    const C* sp = src + t * PITCH;
+    C v[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[r] = sp[PAD ? pad16(j + r * NS) : j + r * NS];
+#pragma unroll
+    for (int r = 1; r < RL; ++r) {
+      C w = tw[r * j * TWS];
+      if constexpr (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dftR<RL, INV>(v);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) store(t, j + r * NS, v[r]);
+  }
+}
+
 // In-place variant: every thread first reads the inputs of all of its
 // butterflies into registers, the workgroup synchronises, then every thread
 // writes its outputs over the same buffer — one buffer instead of two, at

@@ -287,12 +287,10 @@ __device__ __forceinline__ void rows_body(const Common& cm, const JobRec& jb, in
     ((float*)(ws + pick(L.omax, cur)))[r] = om;
     ((float*)(ws + pick(L.pmax, cur)))[r] = pm;
   }
-  float2* res = fft_lds<N, false, R4, 0, PT, PAD>(bufA, bufB, M, tw);
   float2* dst = (float2*)(ws + pick(L.psi, cur));
-  for (int i = tid; i < M * N; i += blockDim.x) {
-    const int p = i / N, cc = i - p * N;
-    dst[p * NN + sidx<N, SINGLE>(r, cc)] = res[p * PT + cc];
-  }
+  fft_lds_store<N, false, R4, 0, PT, PAD>(bufA, bufB, M, tw, [&](int p, int cc, float2 v) {
+    dst[p * NN + sidx<N, SINGLE>(r, cc)] = v;
+  });
   if (SINGLE && i_touch < -3.0e38f) flag_status(jb.status, 0);  // keeps the touch load
 }
 
