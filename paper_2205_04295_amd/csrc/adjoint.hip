@@ -193,11 +193,10 @@ __device__ void adj_p2(const AdjArgs& a, float2* smem) {
       }
   }
   __syncthreads();
-  float2* S = fft_lds<N, false, false, kAdjThreads, PT, true>(W, R, ns * M, tw);
-  for (int i = threadIdx.x; i < ns * M * N; i += kAdjThreads) {
-    const int t = i / N, cc = i - t * N, q = t / M, p = t - q * M;
-    a.Psi[((size_t)(b0 + q) * M + p) * NN + (size_t)r * N + cc] = S[t * PT + cc];
-  }
+  fft_lds_store<N, false, false, kAdjThreads, PT, true>(W, R, ns * M, tw, [&](int t, int cc, float2 v) {
+    const int q = t / M, p = t - q * M;
+    a.Psi[((size_t)(b0 + q) * M + p) * NN + (size_t)r * N + cc] = v;
+  });
 }
 
 // P3 (cols): Psi -> A, loss partial; chi = F^-1((1 - sqrt(I)/A) Psi)
@@ -577,12 +576,9 @@ __device__ void adj_p4(const AdjArgs& a, float2* smem) {
         }
     }
     lds_barrier();
-    float2* H = fft_lds<N, true, false, kAdjThreads, PT, true>(T, S, ns, tw);
-    if (c < N) {
-#pragma unroll
-      for (int q = 0; q < kAdjRowPos; ++q)
-        if (q < ns) a.G[chunk_off(b + q, N) + roff] = H[q * PT + c];
-    }
+    fft_lds_store<N, true, false, kAdjThreads, PT, true>(T, S, ns, tw, [&](int q, int cc, float2 v) {
+      a.G[chunk_off(b + q, N) + (size_t)r * N + cc] = v;
+    });
 #pragma unroll
     for (int q = 0; q < kAdjRowPos; ++q)
       if (q < ns) {

@@ -325,6 +325,40 @@ __device__ __forceinline__ void stage_inplace(C* buf, int nb, const C* __restric
   lds_barrier();
 }
 
+// fft_lds_inplace whose last stage hands its outputs to `store(t, k, v)`
+// (see fft_lds_store); the last stage only reads the buffer.
+template <int N, bool INV, bool R4, int MAXNB, int MINT, int NT = 0, int PITCH = N, bool PAD = false, typename C,
+          typename S>
+__device__ void fft_lds_inplace_store(C* buf, int nb, const C* __restrict__ tw, S store) {
+  using P = typename std::conditional<R4, Plan4<N>, Plan8<N>>::type;
+  constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
+  constexpr int NS = R3 > 1 ? R0 * R1 * R2 : R2 > 1 ? R0 * R1 : R0;
+  constexpr int RL = R3 > 1 ? R3 : R2 > 1 ? R2 : R1;
+  static_assert(NS * RL == N, "plan covers N");
+  stage_inplace<N, R0, 1, INV, (MAXNB * (N / R0) + MINT - 1) / MINT, NT, PITCH, false, PAD>(buf, nb, tw);
+  if constexpr (R2 > 1)
+    stage_inplace<N, R1, R0, INV, (MAXNB * (N / R1) + MINT - 1) / MINT, NT, PITCH, PAD, PAD>(buf, nb, tw);
+  if constexpr (R3 > 1)
+    stage_inplace<N, R2, R0 * R1, INV, (MAXNB * (N / R2) + MINT - 1) / MINT, NT, PITCH, PAD, PAD>(buf, nb, tw);
+  const int total = nb * NS;
+  for (int q = threadIdx.x; q < total; q += wg_threads<NT>()) {
+    const int t = q / NS, j = q - t * NS;
+    const C* sp = buf + t * PITCH;
+    C v[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[r] = sp[PAD ? pad16(j + r * NS) : j + r * NS];
+#pragma unroll
+    for (int r = 1; r < RL; ++r) {
+      C w = tw[r * j];
+      if constexpr (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dftR<RL, INV>(v);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) store(t, j + r * NS, v[r]);
+  }
+}
+
 // Full in-place transforms of `nb` (<= MAXNB) contiguous rows of `buf`
 // with at least `MINT` threads per workgroup (exactly NT when NT > 0).
 // Same contract as fft_lds; the result is in `buf`.

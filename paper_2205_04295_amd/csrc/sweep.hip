@@ -469,18 +469,13 @@ __device__ __forceinline__ void gat_body(const JobRec& jb, int t, float2* smem) 
       ((float*)(jb.ws + pick(L.pmax, cur)))[r0 + s] = pmr[s];
     }
   }
-  float2* res;
-  if constexpr (IP) {
-    fft_lds_inplace<N, false, R4, RP * MM, 256, 0, PT, true>(bufA, RP * M, tw);
-    res = bufA;
-  } else {
-    res = fft_lds<N, false, R4, 0, PT, true>(bufA, bufB, RP * M, tw);
-  }
   float2* dst = (float2*)(jb.ws + pick(L.psi, cur));
-  for (int i = tid; i < RP * M * N; i += blockDim.x) {
-    const int sp = i / N, cc = i - sp * N, s = sp / M, p = sp - s * M;
-    dst[p * NN + (size_t)(r0 + s) * N + cc] = res[sp * PT + cc];
-  }
+  auto store = [&](int sp, int cc, float2 v) {  // transform sp = s M + p
+    const int s = sp / M, p = sp - s * M;
+    dst[p * NN + (size_t)(r0 + s) * N + cc] = v;
+  };
+  if constexpr (IP) fft_lds_inplace_store<N, false, R4, RP * MM, 256, 0, PT, true>(bufA, RP * M, tw, store);
+  else fft_lds_store<N, false, R4, 0, PT, true>(bufA, bufB, RP * M, tw, store);
 }
 
 // Column pass of step t: CW adjacent detector columns per workgroup (all

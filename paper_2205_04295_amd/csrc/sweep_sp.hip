@@ -209,6 +209,7 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
     const float2 ov = orow[min(max(xo, 0), N - 1)];
     v = (rb1 >= 0 && xo >= 0 && xo < N) ? ov : og;
   }
+  float2* cb = (float2*)(ws + L.cb) + (size_t)r * N;
   if (fx_n != 0.f) {
     if (lane) A[c] = v;
     __syncthreads();
@@ -216,10 +217,10 @@ __device__ void sp_rows_gather(const SpArgs& a, int t, int mode, float2* smem) {
     float2* G = (F == A) ? B : A;
     if (lane) G[c] = cmul(F[c], ramp1(c, fx_n, 1.f, N));
     __syncthreads();
-    float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 1, tw);
-    if (lane) v = H[c];
+    fft_lds_store<N, true, false, kSpThreads>(G, F, 1, tw, [&](int, int cc, float2 w) { cb[cc] = w; });
+  } else if (lane) {
+    cb[c] = v;
   }
-  if (lane) ((float2*)(ws + L.cb))[(size_t)r * N + c] = v;
 }
 
 // ---------------------------------------------------------------- C: exit waves
@@ -281,8 +282,10 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
     ((float*)(ws + L.omax[0]))[u] = om;
     ((float*)(ws + L.pmax[0]))[u] = pm;
   }
-  float2* S = fft_lds<N, false, false, kSpThreads>(A, B, M, tw);
+  float2* psi = (float2*)(ws + L.psi[0]);
+  auto store = [&](int p, int kk, float2 v) { psi[p * NN + (size_t)kk * N + u] = v; };
   if (a.fresnel > 0.f) {  // near field: y propagation, F_y^-1 h_y F_y
+    float2* S = fft_lds<N, false, false, kSpThreads>(A, B, M, tw);
     float2* G = (S == A) ? B : A;
     if (lane) {
       const float2 h = fresnel1(k, a.fresnel, -1.f, N);
@@ -291,13 +294,9 @@ __device__ void sp_cols_exit(const SpArgs& a, int t, float2* smem) {
         if (p < M) G[p * N + k] = cmul(S[p * N + k], h);
     }
     __syncthreads();
-    S = fft_lds<N, true, false, kSpThreads>(G, S, M, tw);
-  }
-  float2* psi = (float2*)(ws + L.psi[0]);
-  if (lane) {
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + (size_t)k * N + u] = S[p * N + k];
+    fft_lds_store<N, true, false, kSpThreads>(G, S, M, tw, store);
+  } else {
+    fft_lds_store<N, false, false, kSpThreads>(A, B, M, tw, store);
   }
 }
 
@@ -375,7 +374,7 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
       if (p < M) G[p * N + c] = cscale(F[p * N + c], f);
   }
   __syncthreads();
-  float2* H;
+  auto store = [&](int p, int cc, float2 v) { psi[p * NN + (size_t)r * N + cc] = v; };
   if (near) {  // back along x, F_x^-1 conj(h_x) F_x
     float2* K = fft_lds<N, false, false, kSpThreads>(G, F, M, tw);
     float2* Q = (K == A) ? B : A;
@@ -386,14 +385,9 @@ __device__ void sp_rows_mod(const SpArgs& a, int t, float2* smem) {
         if (p < M) Q[p * N + c] = cmul(K[p * N + c], h);
     }
     __syncthreads();
-    H = fft_lds<N, true, false, kSpThreads>(Q, K, M, tw);
+    fft_lds_store<N, true, false, kSpThreads>(Q, K, M, tw, store);
   } else {
-    H = fft_lds<N, true, false, kSpThreads>(G, F, M, tw);
-  }
-  if (lane) {
-#pragma unroll
-    for (int p = 0; p < MM; ++p)
-      if (p < M) psi[p * NN + (size_t)r * N + c] = H[p * N + c];
+    fft_lds_store<N, true, false, kSpThreads>(G, F, M, tw, store);
   }
   e = wave_sum(e);
   isv = wave_sum(isv);
@@ -486,6 +480,7 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
     if (!a.xcb && recording(a, t)) a.reg_mov[((size_t)jn * N + k) * N + u] = cadd(o, dlt);
   }
   if (bad) flag_status(jb.status, MRPIE_STATUS_NONFINITE);
+  float2* db = (float2*)(ws + L.db) + u;
   if (fy != 0.f) {  // y back-move of delta_o
     if (lane) W[k] = dlt;
     __syncthreads();
@@ -493,10 +488,10 @@ __device__ void sp_cols_update(const SpArgs& a, int t, float2* smem) {
     float2* G = (F == W) ? R : W;
     if (lane) G[k] = cmul(F[k], ramp1(k, fy, -1.f, N));
     __syncthreads();
-    float2* H = fft_lds<N, true, false, kSpThreads>(G, F, 1, tw);
-    if (lane) dlt = H[k];
+    fft_lds_store<N, true, false, kSpThreads>(G, F, 1, tw, [&](int, int kk, float2 v) { db[(size_t)kk * N] = v; });
+  } else if (lane) {
+    db[(size_t)k * N] = dlt;
   }
-  if (lane) ((float2*)(ws + L.db))[(size_t)k * N + u] = dlt;
 }
 
 // ---------------------------------------------------------------- kernels
