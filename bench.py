@@ -39,20 +39,20 @@ FP32_VALU_PEAK_TFS = 78.6
 COUNTERS = {
     "sources": ["paper_2205_04295_amd/csrc/fft.hpp", "paper_2205_04295_amd/csrc/sweep.hip",
                 "paper_2205_04295_amd/csrc/sweep.hpp", "paper_2205_04295_amd/csrc/common.hpp"],
-    "sha256": "f90e5f8f8421f78966e6fff9cbeaa9e89919f8d273a93b2918e567b644add8fe",
+    "sha256": "d70cbb2d92aa7563610c3c4182189f9c3486f2a308be0748dc485b9107d38a98",
     "fetch_factor": 2.000, "write_factor": 1.000,
-    ("k_rows", 1): {"fetch_kib": 3457.5, "write_kib": 4097.6},
+    ("k_rows", 1): {"fetch_kib": 3457.0, "write_kib": 4097.6},
     ("k_cols", 1): {"fetch_kib": 995.5, "write_kib": 1552.0},
-    ("k_rows", 4): {"fetch_kib": 13010.9, "write_kib": 16390.4},
-    ("k_cols", 4): {"fetch_kib": 3700.1, "write_kib": 6160.0},
-    ("k_rows", 8): {"fetch_kib": 26008.1, "write_kib": 32780.7},
-    ("k_cols", 8): {"fetch_kib": 7294.5, "write_kib": 12320.0},
-    ("k_upd", 16): {"fetch_kib": 29180.9, "write_kib": 32865.3},
-    ("k_gat", 16): {"fetch_kib": 16731.8, "write_kib": 24704.0},
-    ("k_cols", 16): {"fetch_kib": 14503.4, "write_kib": 24640.2},
-    ("k_upd", 32): {"fetch_kib": 58242.8, "write_kib": 65731.0},
-    ("k_gat", 32): {"fetch_kib": 33374.9, "write_kib": 49411.2},
-    ("k_cols", 32): {"fetch_kib": 28948.2, "write_kib": 52351.8},
+    ("k_rows", 4): {"fetch_kib": 12999.1, "write_kib": 16390.4},
+    ("k_cols", 4): {"fetch_kib": 3711.1, "write_kib": 6160.0},
+    ("k_rows", 8): {"fetch_kib": 26125.7, "write_kib": 32780.7},
+    ("k_cols", 8): {"fetch_kib": 7305.5, "write_kib": 12320.0},
+    ("k_upd", 16): {"fetch_kib": 29184.4, "write_kib": 32865.3},
+    ("k_gat", 16): {"fetch_kib": 16731.3, "write_kib": 24704.0},
+    ("k_cols", 16): {"fetch_kib": 14507.0, "write_kib": 24640.2},
+    ("k_upd", 32): {"fetch_kib": 58247.7, "write_kib": 65730.9},
+    ("k_gat", 32): {"fetch_kib": 33375.7, "write_kib": 49414.3},
+    ("k_cols", 32): {"fetch_kib": 28950.8, "write_kib": 52259.2},
 }
 
 
